@@ -1,0 +1,98 @@
+"""The seeded input generators: determinism and the structure each recipe promises."""
+import numpy as np
+import pytest
+
+from paper_1303_1379_amd import graphgen as gg
+
+
+def _well_formed(g):
+    assert g.colptr[0] == 0 and len(g.colptr) == g.nc + 1
+    assert (np.diff(g.colptr) >= 0).all()
+    assert g.nnz == len(g.rowind)
+    if g.nnz:
+        assert g.rowind.min() >= 0 and g.rowind.max() < g.nr
+    for c in range(min(g.nc, 3000)):
+        seg = g.rowind[g.colptr[c]:g.colptr[c + 1]]
+        assert (np.diff(seg) > 0).all()
+
+
+def test_uniform2000_deterministic():
+    a, b = gg.workload("uniform2000"), gg.workload("uniform2000")
+    assert a.fnv1a() == b.fnv1a()
+    _well_formed(a)
+    # E[nnz] = 2000 * 2000 * (1 - (1999/2000)^4) ~ 7994
+    assert abs(a.nnz - 7994) < 150
+    assert np.diff(a.colptr).max() <= 4
+
+
+def test_grid_structure():
+    k = 64
+    g, dc, dr = gg.grid5(k, 100, 120, 2, return_masks=True)
+    _well_formed(g)
+    assert dc.sum() == 100 and dr.sum() == 120
+    deg = np.diff(g.colptr)
+    assert (deg[dc] == 0).all()
+    assert not np.isin(g.rowind, np.flatnonzero(dr)).any()
+    full = gg.grid5(k, 0, 0, 2)
+    assert full.nnz == 5 * k * k - 4 * k
+    # entries of column (i,j) are grid neighbours or itself
+    cols, rows = g.edges()
+    di = np.abs(cols // k - rows // k) + np.abs(cols % k - rows % k)
+    assert di.max() <= 1
+
+
+def test_rmat_permutation_preserves_degree_multiset():
+    a = gg.rmat(12, 16 << 12, 5)
+    b = gg.rmat(12, 16 << 12, 5, permute=True)
+    _well_formed(a)
+    _well_formed(b)
+    assert a.nnz == b.nnz
+    assert sorted(np.diff(a.colptr)) == sorted(np.diff(b.colptr))
+    ra = np.bincount(a.rowind, minlength=a.nr)
+    rb = np.bincount(b.rowind, minlength=b.nr)
+    assert sorted(ra) == sorted(rb)
+    # skew: the heaviest column of unpermuted R-MAT (a = .57) is column 0
+    assert np.argmax(np.diff(a.colptr)) == 0
+
+
+def test_rmat_limit_rejects_out_of_range():
+    g = gg.rmat(10, 5000, 8, n_limit=700)
+    assert g.nc == g.nr == 700
+    _well_formed(g)
+
+
+def test_batch_members():
+    for gi in range(12):
+        g = gg.batch_member(4, gi)
+        _well_formed(g)
+        assert 64 <= g.nc <= 65536 and 64 <= g.nr <= 65536
+        deg = np.diff(g.colptr)
+        nempty = int(np.floor(0.02 * g.nc))
+        assert (deg == 0).sum() >= nempty
+        assert deg.max() <= 12
+        if gi % 2 == 1:
+            cols, rows = g.edges()
+            centre = (cols * g.nr) // g.nc
+            assert (np.abs(rows - centre) <= 5).all()
+    a, b = gg.batch_member(4, 3), gg.batch_member(4, 3)
+    assert a.fnv1a() == b.fnv1a()
+
+
+def test_request_trace():
+    gap, n, deg, kind, rs = gg.request_trace(5, 2000)
+    assert (gap > 0).all() and abs(gap.mean() - 1 / 2000) < 1e-4
+    assert n.min() >= 1000 and n.max() <= 1000000
+    assert deg.min() >= 4 and deg.max() <= 16
+    assert 0.4 < kind.mean() < 0.6
+    g = gg.request_graph(int(n[0]), int(deg[0]), 1, int(rs[0]))
+    _well_formed(g)
+
+
+def test_csr_transpose():
+    g = gg.uniform(50, 60, 3, 1)
+    rp, ci = g.csr()
+    assert rp[-1] == g.nnz
+    cols, rows = g.edges()
+    pairs = set(zip(cols.tolist(), rows.tolist()))
+    pairs2 = {(int(ci[j]), r) for r in range(g.nr) for j in range(rp[r], rp[r + 1])}
+    assert pairs == pairs2
