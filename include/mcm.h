@@ -1,0 +1,222 @@
+/*
+ * mcm.h -- maximum-cardinality matching in bipartite graphs on one MI355X
+ * (gfx950), after Deveci, Kaya, Ucar and Catalyurek, "GPU accelerated
+ * maximum cardinality matching algorithms for bipartite graphs".
+ *
+ * Method (paper, section 3): starting from a given (typically greedy)
+ * matching, repeat phases until a phase finds nothing:
+ *   - a level-synchronous alternating BFS from every unmatched column over
+ *     the column-compressed pattern, recording for each reached row the
+ *     column it was reached from (predecessor) and, per BFS tree, its root
+ *     column (Algorithm 2 "GPUBFS"; Algorithm 4 "GPUBFS-WR" adds the root
+ *     and stops expanding a tree once its root has found an unmatched row);
+ *   - Alternate (Algorithm 3): from every unmatched row found, flip the
+ *     matched/unmatched edges back along the predecessor chain, stopping
+ *     where another flip already passed;
+ *   - FixMatching: unmatch every row whose column no longer points back.
+ * APFB (the default driver) keeps expanding BFS levels until the frontier
+ * is empty; APsB stops at the first level that finds an unmatched row
+ * (Algorithm 1 and the text after it).  On termination no augmenting path
+ * is left, so the matching is maximum (Berge's theorem, section 2).
+ *
+ * Conventions shared by every entry point
+ *   - Graph: CSC.  colptr[ncols+1] with colptr[0] = 0, non-decreasing,
+ *     colptr[ncols] = nnz < 2^31; rowind[nnz] with 0 <= rowind[j] < nrows.
+ *     Rows of a column may come in any order; duplicates are tolerated.
+ *   - Matching: cmatch[ncols], rmatch[nrows], int32; cmatch[c] = r and
+ *     rmatch[r] = c for a matched pair, -1 for an unmatched vertex (the
+ *     problem statement of Algorithm 1).
+ *   - Unless stated otherwise, array arguments are DEVICE pointers owned by
+ *     the caller; the library never frees caller memory and keeps no
+ *     pointer to it after the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls that return a result synchronise that stream before returning.
+ *   - Errors: a negative return value is an mcm_status; mcm_strerror()
+ *     gives the message of the calling thread's last error.  No C++
+ *     exception crosses this interface.
+ *   - Concurrency: entry points may be called from several host threads;
+ *     calls that share the library workspace are serialised internally.
+ */
+#ifndef MCM_H
+#define MCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCM_OK = 0,
+    MCM_EINVAL = -1,     /* bad argument or malformed CSC (see mcm_set_option "validate") */
+    MCM_ENOMEM = -2,     /* device or host allocation failed */
+    MCM_EHIP = -3,       /* a HIP runtime call failed */
+    MCM_EBADINIT = -4,   /* initial matching inconsistent or not on edges (validate=1 only) */
+    MCM_EINTERNAL = -5,  /* watchdog: a phase or level bound was exceeded, or a device wait timed out */
+    MCM_ENOTMAX = -6     /* mcm_konig_cover: the given matching admits an augmenting path */
+} mcm_status;
+
+/*
+ * mcm_match -- maximum matching of one graph (paper, Algorithm 1 driven as
+ * APFB by default, BFS kernel GPUBFS-WR of Algorithm 4, Alternate of
+ * Algorithm 3, FixMatching).
+ *
+ *   ncols, nrows   number of column and row vertices (>= 0)
+ *   colptr         [ncols+1] device, CSC column pointers
+ *   rowind         [nnz] device, row indices; may be NULL only when nnz == 0
+ *   init_cmatch    [ncols] device, initial matching, or NULL
+ *   init_rmatch    [nrows] device, or NULL; both NULL = empty matching,
+ *                  exactly one NULL is MCM_EINVAL.  Must be a matching of
+ *                  the graph (checked only with option validate=1).
+ *   out_cmatch     [ncols] device, receives a maximum matching; may alias
+ *                  init_cmatch
+ *   out_rmatch     [nrows] device; may alias init_rmatch
+ *   stream         hipStream_t as void*
+ *
+ * Returns |M| >= 0, or a negative mcm_status.  ncols == 0 or nrows == 0
+ * returns 0 with both outputs filled with -1.  The matching returned is a
+ * maximum matching; which one depends on the schedule of the concurrent
+ * flips (the paper's Alternate races by design), its size does not.
+ */
+int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                  const int32_t *init_cmatch, const int32_t *init_rmatch,
+                  int32_t *out_cmatch, int32_t *out_rmatch, void *stream);
+
+/*
+ * One graph of a batch.  Offsets are element offsets into the packed
+ * arrays of mcm_match_batched: column pointers of graph g are
+ * colptr_all[colptr_off .. colptr_off+ncols] (ncols+1 entries, local
+ * values starting at 0), its rows rowind_all[rowind_off ..) (local row
+ * ids), its column state *_cmatch_all[col_off ..) and row state
+ * *_rmatch_all[row_off ..).
+ */
+typedef struct {
+    int32_t ncols, nrows;
+    int64_t colptr_off, rowind_off, col_off, row_off;
+} mcm_graph;
+
+/*
+ * mcm_match_batched -- maximum matchings of many independent graphs in one
+ * device launch (one persistent kernel drains a work queue of graphs,
+ * largest first; each graph is matched by one workgroup with the same
+ * phases as mcm_match).  Defined to equal calling mcm_match on each graph:
+ * the per-graph cardinalities are identical.
+ *
+ *   ngraphs            >= 0
+ *   graphs             [ngraphs] HOST array of descriptors (copied)
+ *   colptr_all, rowind_all           device, packed CSC of every graph
+ *   init_cmatch_all, init_rmatch_all device, packed initial matchings, or
+ *                                    both NULL (all empty)
+ *   out_cmatch_all, out_rmatch_all   device, packed outputs (may alias init)
+ *   out_card           [ngraphs] HOST, receives |M_g|, or NULL
+ *   stream             hipStream_t as void*
+ *
+ * Returns sum_g |M_g| >= 0 or a negative mcm_status.  Graph ranges must
+ * not overlap in the output arrays.
+ */
+int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs,
+                          const int32_t *colptr_all, const int32_t *rowind_all,
+                          const int32_t *init_cmatch_all, const int32_t *init_rmatch_all,
+                          int32_t *out_cmatch_all, int32_t *out_rmatch_all,
+                          int64_t *out_card, void *stream);
+
+/*
+ * mcm_konig_cover -- minimum vertex cover certifying a maximum matching
+ * (Konig's theorem; section 2 states the Berge criterion it rests on).
+ * Runs one complete alternating BFS from every unmatched column (GPUBFS,
+ * no early exit).  If it reaches an unmatched row the matching is not
+ * maximum and MCM_ENOTMAX is returned.  Otherwise, with Z_C the reached
+ * columns: col_in_cover[c] = 1 iff c is matched and not in Z_C, and
+ * row_in_cover[r] = 1 iff r is adjacent to Z_C.
+ *
+ *   cmatch, rmatch      device, a matching of the graph (not modified)
+ *   col_in_cover        [ncols] device uint8 output
+ *   row_in_cover        [nrows] device uint8 output
+ * Returns |K| (equal to |M|) or a negative mcm_status.
+ */
+int64_t mcm_konig_cover(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                        const int32_t *cmatch, const int32_t *rmatch,
+                        uint8_t *col_in_cover, uint8_t *row_in_cover, void *stream);
+
+/*
+ * mcm_bfs_levels -- one complete alternating BFS phase from every unmatched
+ * column of the given matching, without early exit and without
+ * augmentation (the level sets that GPUBFS of Algorithm 2 builds one
+ * launch per level).  Inspection and testing aid.
+ *
+ *   col_level  [ncols] device output: BFS level of each column (unmatched
+ *              columns 0, a column reached through its matched row one more
+ *              than the column that reached that row), -1 if not reached
+ *   row_pred   [nrows] device output: the column that reached each row
+ *              (one of several when several columns of the same level are
+ *              adjacent), -1 if not reached
+ * Returns the number of unmatched rows reached, or a negative mcm_status.
+ */
+int64_t mcm_bfs_levels(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                       const int32_t *cmatch, const int32_t *rmatch,
+                       int32_t *col_level, int32_t *row_pred, void *stream);
+
+/*
+ * mcm_cheap_init_host -- the greedy initial matching that precedes every
+ * run in the paper's experiments (section 4): columns in index order, each
+ * takes the first row of its stored adjacency that is still unmatched.
+ * HOST arrays; cmatch[ncols] and rmatch[nrows] are overwritten.
+ * Returns |M0| or MCM_EINVAL.
+ */
+int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                            int32_t *cmatch, int32_t *rmatch);
+
+/*
+ * mcm_set_option / mcm_get_option -- process-wide settings (strings).
+ *   "driver"    "apfb" (default) | "apsb"      Algorithm 1 with or without
+ *                                              the stop at the first level
+ *                                              that finds an unmatched row
+ *   "bfs"       "wr" (default) | "plain"       GPUBFS-WR (Algorithm 4) or
+ *                                              GPUBFS (Algorithm 2)
+ *   "mapping"   "auto" (default) | "thread" | "wave"
+ *                                              frontier column per lane, or
+ *                                              edges of 64 columns balanced
+ *                                              across a wavefront
+ *   "loop"      "auto" (default) | "device" | "host"
+ *                                              BFS level loop in one
+ *                                              persistent launch with grid
+ *                                              barriers, or one launch per
+ *                                              level
+ *   "validate"  "0" (default) | "1"            check CSC and init on device
+ *   "stats"     "0" (default) | "1"            count scanned edges etc.
+ *   "tuning"    path of an autotuner cache file (JSON) or ""
+ * Return MCM_OK or MCM_EINVAL (unknown key or value).  mcm_get_option
+ * writes the current value into buf (NUL-terminated, truncated to len).
+ */
+int mcm_set_option(const char *key, const char *value);
+int mcm_get_option(const char *key, char *buf, int32_t len);
+
+/* Counters of the last mcm_match / mcm_match_batched call on this process. */
+typedef struct {
+    int64_t phases;          /* phases run, including the last one that found nothing */
+    int64_t levels;          /* BFS levels expanded, summed over phases */
+    int64_t edges_scanned;   /* adjacency entries read by BFS (stats=1) */
+    int64_t cols_expanded;   /* frontier columns expanded (stats=1) */
+    int64_t cols_claimed;    /* columns inserted into a next frontier (stats=1) */
+    int64_t rows_found;      /* unmatched rows reached, summed over phases (stats=1) */
+    int64_t alt_steps;       /* Alternate loop iterations (stats=1) */
+    int64_t fix_resets;      /* rows reset by FixMatching (stats=1) */
+    int64_t init_card;       /* |M| of the initial matching */
+    int64_t card;            /* |M| returned */
+    double  kernel_ms;       /* device time of the matching, HIP events */
+    int32_t loop;            /* 0 = device-side level loop, 1 = host-side */
+    int32_t mapping;         /* 0 = thread, 1 = wave */
+} mcm_stats;
+
+int mcm_last_stats(mcm_stats *out);
+
+/* Message for a status code, or the calling thread's last error message. */
+const char *mcm_strerror(int64_t status);
+
+/* Library version string. */
+const char *mcm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCM_H */

@@ -1,0 +1,732 @@
+// Host driver and C ABI of libmcm.so (declared in include/mcm.h).
+//
+// Responsibilities: argument checks, the library-owned device workspace,
+// choice of launch form (one workgroup for small graphs, a persistent
+// cooperative launch, or a host-driven loop of per-level launches), error
+// reporting, options and counters.  All matching arithmetic runs in the
+// kernels of mcm_kernels.hip; the only host-side computation is the greedy
+// initial matching, offered as its own entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mcm.h"
+#include "mcm_internal.h"
+
+namespace mcm {
+hipError_t launch_setup(const DevGraph &, const int32_t *, const int32_t *, uint32_t *, uint32_t, hipStream_t);
+hipError_t launch_validate(int32_t, int32_t, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
+                           uint32_t *, hipStream_t);
+hipError_t persistent_occupancy(bool, int, int *);
+hipError_t launch_persistent(const DevGraph &, uint32_t *, const RunOpt &, bool, int, int, hipStream_t);
+hipError_t launch_init_roots(const DevGraph &, uint32_t *, uint32_t, hipStream_t);
+hipError_t launch_level(const DevGraph &, uint32_t *, uint32_t, uint32_t, int, uint32_t, bool, int, hipStream_t);
+hipError_t launch_alternate(const DevGraph &, uint32_t *, uint32_t, uint32_t, hipStream_t);
+hipError_t launch_fix(const DevGraph &, uint32_t *, uint32_t, hipStream_t);
+hipError_t launch_finish(const DevGraph &, int32_t *, uint32_t *, hipStream_t);
+hipError_t launch_cover(const DevGraph &, uint32_t, uint8_t *, uint8_t *, uint32_t *, hipStream_t);
+hipError_t launch_export_pred(const DevGraph &, uint32_t, int32_t *, hipStream_t);
+hipError_t launch_match_wg(const BatchDesc *, const int32_t *, int32_t, const int32_t *, const int32_t *,
+                           const int32_t *, const int32_t *, int32_t *, int32_t *, uint64_t *, int32_t *, uint32_t *,
+                           int4 *, int32_t *, int64_t *, uint32_t *, const RunOpt &, bool, int, int, hipStream_t);
+hipError_t launch_zero_ctrl(uint32_t *, hipStream_t);
+}  // namespace mcm
+
+using namespace mcm;
+
+namespace {
+
+// ------------------------------------------------------------------ errors
+thread_local std::string t_err;
+
+int64_t fail(int64_t code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(MCM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+// ------------------------------------------------------------------ options
+struct Options {
+    bool apsb = false;        // driver
+    bool wr = true;           // bfs
+    int mapping = 2;          // 0 thread, 1 wave, 2 auto
+    int loop = 2;             // 0 device, 1 host, 2 auto
+    bool validate = false;
+    bool stats = false;
+    std::string tuning;
+    int block = 1024;         // persistent block size
+    int blocks_per_cu = 1;    // 0 = occupancy limit
+    int wg_block = 512;       // one-workgroup matcher block size
+    int64_t wg_threshold = 16384;  // nc + nr at or below which one workgroup matches alone
+    double timeout_s = 20.0;  // device barrier wait limit
+};
+Options g_opt;
+std::mutex g_opt_mu;
+
+Options opts()
+{
+    std::lock_guard<std::mutex> lk(g_opt_mu);
+    return g_opt;
+}
+
+// ------------------------------------------------------------------ device info + workspace
+struct DevInfo {
+    int ncu = 0;
+    double clock_khz = 100000.0;
+};
+
+struct Workspace {
+    int device = -1;
+    size_t cap_nc = 0, cap_nr = 0;
+    uint64_t *rw = nullptr;
+    int32_t *pred = nullptr;
+    uint32_t *cdone = nullptr;
+    int4 *fq = nullptr;
+    int32_t *ends = nullptr;
+    int32_t *cwork = nullptr;
+    uint32_t *ctrl = nullptr;
+    BatchDesc *desc = nullptr;
+    size_t cap_desc = 0;
+    int32_t *order = nullptr;
+    int64_t *card = nullptr;
+    uint32_t *h_ctrl = nullptr;  // pinned
+    BatchDesc *h_desc = nullptr; // pinned
+    int32_t *h_order = nullptr;  // pinned
+    int64_t *h_card = nullptr;   // pinned
+    size_t cap_hdesc = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevInfo info;
+};
+
+std::mutex g_ws_mu;
+Workspace g_ws[64];
+mcm_stats g_stats;
+std::mutex g_stats_mu;
+
+void free_dev(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+int64_t ensure_base(Workspace &w, int dev)
+{
+    if (w.device == dev && w.ctrl) return 0;
+    w.device = dev;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    w.info.ncu = prop.multiProcessorCount;
+    int rate = 0;
+    if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate > 0)
+        w.info.clock_khz = rate;
+    HIPCHK(hipMalloc(&w.ctrl, (size_t)L_NLINES * 128));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&w.h_ctrl), (size_t)L_NLINES * 128, hipHostMallocDefault));
+    HIPCHK(hipEventCreate(&w.ev0));
+    HIPCHK(hipEventCreate(&w.ev1));
+    return 0;
+}
+
+int64_t ensure_graph(Workspace &w, size_t nc, size_t nr)
+{
+    if (nc > w.cap_nc) {
+        free_dev(w.cdone); free_dev(w.fq); free_dev(w.cwork);
+        w.cdone = nullptr; w.fq = nullptr; w.cwork = nullptr;
+        size_t cap = std::max(nc, w.cap_nc + w.cap_nc / 2);
+        if (hipMalloc(&w.cdone, sizeof(uint32_t) * cap) != hipSuccess ||
+            hipMalloc(&w.fq, sizeof(int4) * 2 * cap) != hipSuccess ||
+            hipMalloc(&w.cwork, sizeof(int32_t) * cap) != hipSuccess) {
+            w.cap_nc = 0;
+            return fail(MCM_ENOMEM, "workspace allocation for %zu columns failed", nc);
+        }
+        w.cap_nc = cap;
+    }
+    if (nr > w.cap_nr) {
+        free_dev(w.rw); free_dev(w.pred); free_dev(w.ends);
+        w.rw = nullptr; w.pred = nullptr; w.ends = nullptr;
+        size_t cap = std::max(nr, w.cap_nr + w.cap_nr / 2);
+        if (hipMalloc(&w.rw, sizeof(uint64_t) * cap) != hipSuccess ||
+            hipMalloc(&w.pred, sizeof(int32_t) * cap) != hipSuccess ||
+            hipMalloc(&w.ends, sizeof(int32_t) * cap) != hipSuccess) {
+            w.cap_nr = 0;
+            return fail(MCM_ENOMEM, "workspace allocation for %zu rows failed", nr);
+        }
+        w.cap_nr = cap;
+    }
+    return 0;
+}
+
+int64_t ensure_desc(Workspace &w, size_t n)
+{
+    if (n <= w.cap_desc) return 0;
+    free_dev(w.desc); free_dev(w.order); free_dev(w.card);
+    if (w.h_desc) (void)hipHostFree(w.h_desc);
+    if (w.h_order) (void)hipHostFree(w.h_order);
+    if (w.h_card) (void)hipHostFree(w.h_card);
+    w.desc = nullptr; w.order = nullptr; w.card = nullptr; w.h_desc = nullptr; w.h_order = nullptr; w.h_card = nullptr;
+    size_t cap = std::max(n, (size_t)64);
+    if (hipMalloc(&w.desc, sizeof(BatchDesc) * cap) != hipSuccess ||
+        hipMalloc(&w.order, sizeof(int32_t) * cap) != hipSuccess ||
+        hipMalloc(&w.card, sizeof(int64_t) * cap) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&w.h_desc), sizeof(BatchDesc) * cap, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&w.h_order), sizeof(int32_t) * cap, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&w.h_card), sizeof(int64_t) * cap, hipHostMallocDefault) != hipSuccess) {
+        w.cap_desc = 0;
+        return fail(MCM_ENOMEM, "descriptor allocation for %zu graphs failed", n);
+    }
+    w.cap_desc = cap;
+    return 0;
+}
+
+uint32_t *ctrl_line(uint32_t *ctrl, int l) { return ctrl + l * kLineWords; }
+uint64_t ctrl_stat(uint32_t *ctrl, int s) { return reinterpret_cast<uint64_t *>(ctrl_line(ctrl, L_STAT0))[s * 16]; }
+
+RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info)
+{
+    RunOpt r;
+    r.flags = flags;
+    r.max_phases = (uint32_t)std::min<int64_t>(nc + 2, 0x7fffffff);
+    r.max_levels = (uint32_t)std::min<int64_t>(nc + 2, 0x7fffffff);
+    r.timeout = (uint64_t)(o.timeout_s * info.clock_khz * 1000.0);
+    return r;
+}
+
+// Runs the phase loop on one graph whose state was set up by launch_setup.
+// flags decides APFB/APsB, WR, NOAUG.  Returns 0 or a negative status; the
+// control block is copied to w.h_ctrl (stream synchronised).
+int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t flags, hipStream_t st, int *loop_used)
+{
+    const bool wave = (flags & F_WAVE) != 0;
+    int loop = o.loop;
+    if (loop == 2) loop = 0;
+    *loop_used = loop;
+    RunOpt ro = run_opt(o, flags, g.nc, w.info);
+    if (loop == 0) {
+        int occ = 0;
+        HIPCHK(persistent_occupancy(wave, o.block, &occ));
+        if (occ < 1) return fail(MCM_EHIP, "persistent kernel cannot be resident with block %d", o.block);
+        int per_cu = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
+        int blocks = w.info.ncu * per_cu;
+        HIPCHK(launch_persistent(g, w.ctrl, ro, wave, blocks, o.block, st));
+        HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return 0;
+    }
+    // host-driven loop: one launch per step, control block read back after each level
+    uint32_t *hc = w.h_ctrl;
+    auto readback = [&]() -> int64_t {
+        HIPCHK(hipMemcpyAsync(hc, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return 0;
+    };
+    uint32_t phases = 0, levels = 0;
+    int64_t rc;
+    for (uint32_t ph = 1;; ++ph) {
+        if (ph > ro.max_phases) return fail(MCM_EINTERNAL, "phase bound exceeded");
+        HIPCHK(launch_init_roots(g, w.ctrl, flags, st));
+        if ((rc = readback())) return rc;
+        uint32_t n = *ctrl_line(hc, L_FCOUNT0);
+        int L = 0;
+        while (n > 0) {
+            if ((uint32_t)L > ro.max_levels) return fail(MCM_EINTERNAL, "level bound exceeded");
+            HIPCHK(launch_level(g, w.ctrl, n, ph, L, flags, wave, w.info.ncu * 8, st));
+            ++levels;
+            if ((rc = readback())) return rc;
+            if ((flags & F_APSB) && *ctrl_line(hc, L_FOUND0 + (L % 3))) break;
+            n = *ctrl_line(hc, L_FCOUNT0 + ((L + 1) % 3));
+            ++L;
+        }
+        phases = ph;
+        const uint32_t ne = *ctrl_line(hc, L_NENDS);
+        if (ne == 0 || (flags & F_NOAUG)) break;
+        HIPCHK(launch_alternate(g, w.ctrl, ne, flags, st));
+        HIPCHK(launch_fix(g, w.ctrl, flags, st));
+    }
+    // record counts in the device control block so both loops report alike
+    hc[L_PHASE * kLineWords] = phases;
+    hc[L_LEVELS * kLineWords] = levels;
+    HIPCHK(hipMemcpyAsync(ctrl_line(w.ctrl, L_PHASE), ctrl_line(hc, L_PHASE), 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctrl_line(w.ctrl, L_LEVELS), ctrl_line(hc, L_LEVELS), 4, hipMemcpyHostToDevice, st));
+    if ((rc = readback())) return rc;
+    return 0;
+}
+
+uint32_t base_flags(const Options &o, int64_t nc, int64_t nnz_hint)
+{
+    uint32_t f = 0;
+    if (o.wr) f |= F_WR;
+    if (o.apsb) f |= F_APSB;
+    if (o.stats) f |= F_STATS;
+    bool wave = o.mapping == 1;
+    if (o.mapping == 2) wave = true;
+    (void)nc; (void)nnz_hint;
+    if (wave) f |= F_WAVE;
+    return f;
+}
+
+int current_device(int *dev)
+{
+    return hipGetDevice(dev) == hipSuccess ? 0 : -1;
+}
+
+void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int loop, uint32_t flags)
+{
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    mcm_stats s{};
+    s.phases = *ctrl_line(hc, L_PHASE);
+    s.levels = *ctrl_line(hc, L_LEVELS);
+    s.edges_scanned = (int64_t)ctrl_stat(hc, S_EDGES);
+    s.cols_expanded = (int64_t)ctrl_stat(hc, S_EXPANDED);
+    s.cols_claimed = (int64_t)ctrl_stat(hc, S_CLAIMED);
+    s.rows_found = (int64_t)ctrl_stat(hc, S_FOUND);
+    s.alt_steps = (int64_t)ctrl_stat(hc, S_ALT);
+    s.fix_resets = (int64_t)ctrl_stat(hc, S_FIX);
+    s.init_card = init_card;
+    s.card = card;
+    s.kernel_ms = ms;
+    s.loop = loop;
+    s.mapping = (flags & F_WAVE) ? 1 : 0;
+    g_stats = s;
+}
+
+int64_t check_graph_args(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind)
+{
+    if (nc < 0 || nr < 0) return fail(MCM_EINVAL, "ncols=%d nrows=%d must be >= 0", nc, nr);
+    if (nc > 0 && !colptr) return fail(MCM_EINVAL, "colptr is NULL");
+    (void)rowind;
+    return 0;
+}
+
+// rowind may be NULL only for a graph without edges: checked by reading
+// colptr[nc] before any kernel could touch rowind.
+int64_t check_null_rowind(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind, hipStream_t st)
+{
+    if (rowind || nc == 0 || nr == 0) return 0;
+    int32_t nnz = -1;
+    HIPCHK(hipMemcpyAsync(&nnz, colptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (nnz != 0) return fail(MCM_EINVAL, "rowind is NULL but colptr[ncols] = %d", nnz);
+    return 0;
+}
+
+// One workgroup matches one graph (small graphs).
+int64_t run_single_wg(Workspace &w, const Options &o, int32_t nc, int32_t nr, const int32_t *colptr,
+                      const int32_t *rowind, const int32_t *ic, const int32_t *ir, int32_t *oc, int32_t *orr,
+                      uint32_t flags, hipStream_t st)
+{
+    int64_t rc;
+    if ((rc = ensure_desc(w, 1))) return rc;
+    w.h_desc[0] = BatchDesc{nc, nr, 0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(w.desc, w.h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_zero_ctrl(w.ctrl, st));
+    RunOpt ro = run_opt(o, flags, nc, w.info);
+    HIPCHK(hipEventRecord(w.ev0, st));
+    HIPCHK(launch_match_wg(w.desc, nullptr, 1, colptr, rowind, ic, ir, oc, orr, w.rw, w.pred, w.cdone, w.fq, w.ends,
+                           w.card, w.ctrl, ro, (flags & F_WAVE) != 0, 1, o.wg_block, st));
+    HIPCHK(hipEventRecord(w.ev1, st));
+    HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *mcm_version(void) { return "mcm-gfx950 0.1"; }
+
+const char *mcm_strerror(int64_t status)
+{
+    if (status < 0 && !t_err.empty()) return t_err.c_str();
+    switch (status) {
+    case MCM_OK: return "ok";
+    case MCM_EINVAL: return "invalid argument";
+    case MCM_ENOMEM: return "out of memory";
+    case MCM_EHIP: return "HIP runtime error";
+    case MCM_EBADINIT: return "initial matching is not a matching of the graph";
+    case MCM_EINTERNAL: return "internal bound exceeded (watchdog)";
+    case MCM_ENOTMAX: return "matching is not maximum";
+    default: return status >= 0 ? "ok" : "unknown error";
+    }
+}
+
+int mcm_set_option(const char *key, const char *value)
+{
+    if (!key || !value) return (int)fail(MCM_EINVAL, "NULL option key or value");
+    std::lock_guard<std::mutex> lk(g_opt_mu);
+    std::string k(key), v(value);
+    auto as_int = [&](int64_t lo, int64_t hi, int64_t *out) -> bool {
+        char *end = nullptr;
+        long long x = strtoll(value, &end, 10);
+        if (!end || *end || end == value || x < lo || x > hi) return false;
+        *out = x;
+        return true;
+    };
+    int64_t x = 0;
+    if (k == "driver") {
+        if (v == "apfb") g_opt.apsb = false;
+        else if (v == "apsb") g_opt.apsb = true;
+        else return (int)fail(MCM_EINVAL, "driver must be apfb or apsb");
+    } else if (k == "bfs") {
+        if (v == "wr") g_opt.wr = true;
+        else if (v == "plain") g_opt.wr = false;
+        else return (int)fail(MCM_EINVAL, "bfs must be wr or plain");
+    } else if (k == "mapping") {
+        if (v == "thread") g_opt.mapping = 0;
+        else if (v == "wave") g_opt.mapping = 1;
+        else if (v == "auto") g_opt.mapping = 2;
+        else return (int)fail(MCM_EINVAL, "mapping must be thread, wave or auto");
+    } else if (k == "loop") {
+        if (v == "device") g_opt.loop = 0;
+        else if (v == "host") g_opt.loop = 1;
+        else if (v == "auto") g_opt.loop = 2;
+        else return (int)fail(MCM_EINVAL, "loop must be device, host or auto");
+    } else if (k == "validate") {
+        if (v == "0" || v == "1") g_opt.validate = v == "1";
+        else return (int)fail(MCM_EINVAL, "validate must be 0 or 1");
+    } else if (k == "stats") {
+        if (v == "0" || v == "1") g_opt.stats = v == "1";
+        else return (int)fail(MCM_EINVAL, "stats must be 0 or 1");
+    } else if (k == "tuning") {
+        g_opt.tuning = v;
+    } else if (k == "block") {
+        if (!as_int(64, 1024, &x) || x % 64) return (int)fail(MCM_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+        g_opt.block = (int)x;
+    } else if (k == "blocks_per_cu") {
+        if (!as_int(0, 32, &x)) return (int)fail(MCM_EINVAL, "blocks_per_cu must be in [0, 32]");
+        g_opt.blocks_per_cu = (int)x;
+    } else if (k == "wg_block") {
+        if (!as_int(64, 1024, &x) || x % 64) return (int)fail(MCM_EINVAL, "wg_block must be a multiple of 64 in [64, 1024]");
+        g_opt.wg_block = (int)x;
+    } else if (k == "wg_threshold") {
+        if (!as_int(0, (int64_t)1 << 40, &x)) return (int)fail(MCM_EINVAL, "wg_threshold must be >= 0");
+        g_opt.wg_threshold = x;
+    } else if (k == "timeout_s") {
+        char *end = nullptr;
+        double d = strtod(value, &end);
+        if (!end || *end || !(d > 0.0 && d <= 600.0)) return (int)fail(MCM_EINVAL, "timeout_s must be in (0, 600]");
+        g_opt.timeout_s = d;
+    } else {
+        return (int)fail(MCM_EINVAL, "unknown option '%s'", key);
+    }
+    return MCM_OK;
+}
+
+int mcm_get_option(const char *key, char *buf, int32_t len)
+{
+    if (!key || !buf || len <= 0) return (int)fail(MCM_EINVAL, "bad arguments");
+    Options o = opts();
+    std::string k(key), v;
+    static const char *maps[] = {"thread", "wave", "auto"};
+    static const char *loops[] = {"device", "host", "auto"};
+    if (k == "driver") v = o.apsb ? "apsb" : "apfb";
+    else if (k == "bfs") v = o.wr ? "wr" : "plain";
+    else if (k == "mapping") v = maps[o.mapping];
+    else if (k == "loop") v = loops[o.loop];
+    else if (k == "validate") v = o.validate ? "1" : "0";
+    else if (k == "stats") v = o.stats ? "1" : "0";
+    else if (k == "tuning") v = o.tuning;
+    else if (k == "block") v = std::to_string(o.block);
+    else if (k == "blocks_per_cu") v = std::to_string(o.blocks_per_cu);
+    else if (k == "wg_block") v = std::to_string(o.wg_block);
+    else if (k == "wg_threshold") v = std::to_string(o.wg_threshold);
+    else if (k == "timeout_s") v = std::to_string(o.timeout_s);
+    else return (int)fail(MCM_EINVAL, "unknown option '%s'", key);
+    snprintf(buf, (size_t)len, "%s", v.c_str());
+    return MCM_OK;
+}
+
+int mcm_last_stats(mcm_stats *out)
+{
+    if (!out) return (int)fail(MCM_EINVAL, "NULL stats pointer");
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    *out = g_stats;
+    return MCM_OK;
+}
+
+int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind, int32_t *cmatch,
+                            int32_t *rmatch)
+{
+    if (ncols < 0 || nrows < 0 || (ncols > 0 && (!colptr || !cmatch)) || (nrows > 0 && !rmatch))
+        return fail(MCM_EINVAL, "bad arguments to mcm_cheap_init_host");
+    std::fill(cmatch, cmatch + ncols, -1);
+    std::fill(rmatch, rmatch + nrows, -1);
+    int64_t card = 0;
+    for (int32_t c = 0; c < ncols; ++c) {
+        const int32_t b = colptr[c], e = colptr[c + 1];
+        if (e < b) return fail(MCM_EINVAL, "colptr decreases at column %d", c);
+        for (int32_t j = b; j < e; ++j) {
+            const int32_t r = rowind[j];
+            if (r < 0 || r >= nrows) return fail(MCM_EINVAL, "row index %d out of range at %d", r, j);
+            if (rmatch[r] < 0) {
+                rmatch[r] = c;
+                cmatch[c] = r;
+                ++card;
+                break;
+            }
+        }
+    }
+    return card;
+}
+
+int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                  const int32_t *init_cmatch, const int32_t *init_rmatch, int32_t *out_cmatch, int32_t *out_rmatch,
+                  void *stream)
+{
+    int64_t rc;
+    if ((rc = check_graph_args(ncols, nrows, colptr, rowind))) return rc;
+    if ((init_cmatch == nullptr) != (init_rmatch == nullptr))
+        return fail(MCM_EINVAL, "init_cmatch and init_rmatch must both be NULL or both be given");
+    if ((ncols > 0 && !out_cmatch) || (nrows > 0 && !out_rmatch)) return fail(MCM_EINVAL, "output array is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if ((rc = check_null_rowind(ncols, nrows, colptr, rowind, st))) return rc;
+    if (ncols == 0 || nrows == 0) {
+        if (ncols > 0) HIPCHK(hipMemsetAsync(out_cmatch, 0xff, sizeof(int32_t) * ncols, st));
+        if (nrows > 0) HIPCHK(hipMemsetAsync(out_rmatch, 0xff, sizeof(int32_t) * nrows, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return 0;
+    }
+    int dev = 0;
+    if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
+    const Options o = opts();
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[dev];
+    if ((rc = ensure_base(w, dev))) return rc;
+    if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows))) return rc;
+
+    if (o.validate) {
+        HIPCHK(launch_zero_ctrl(w.ctrl, st));
+        HIPCHK(launch_validate(ncols, nrows, colptr, rowind, init_cmatch, init_rmatch, w.ctrl, st));
+        HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
+        if (s == MCM_EINVAL) return fail(MCM_EINVAL, "malformed CSC input");
+        if (s == MCM_EBADINIT) return fail(MCM_EBADINIT, "initial matching is inconsistent or not on edges");
+    }
+
+    const uint32_t flags = base_flags(o, ncols, 0);
+    int loop = 0;
+    float ms = 0.f;
+    int64_t init_card = -1;
+    if ((int64_t)ncols + nrows <= o.wg_threshold) {
+        if ((rc = run_single_wg(w, o, ncols, nrows, colptr, rowind, init_cmatch, init_rmatch, out_cmatch, out_rmatch,
+                                flags, st)))
+            return rc;
+        HIPCHK(hipEventElapsedTime(&ms, w.ev0, w.ev1));
+        loop = 2;
+        int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
+        int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
+        record_stats(w.h_ctrl, init_card, card, ms, loop, flags);
+        if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
+        return card;
+    }
+
+    DevGraph g;
+    g.colptr = colptr;
+    g.rowind = rowind;
+    g.nc = ncols;
+    g.nr = nrows;
+    g.cmatch = out_cmatch;
+    g.rw = w.rw;
+    g.pred = w.pred;
+    g.cdone = w.cdone;
+    g.fq0 = w.fq;
+    g.fq1 = w.fq + ncols;
+    g.ends = w.ends;
+    g.clevel = nullptr;
+    HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, flags, st));
+    HIPCHK(hipEventRecord(w.ev0, st));
+    if ((rc = run_graph(w, o, g, flags, st, &loop))) return rc;
+    HIPCHK(hipEventRecord(w.ev1, st));
+    HIPCHK(launch_finish(g, out_rmatch, w.ctrl, st));
+    HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipEventElapsedTime(&ms, w.ev0, w.ev1));
+    const int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
+    const int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
+    record_stats(w.h_ctrl, init_card, card, ms, loop, flags);
+    if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
+    return card;
+}
+
+// Shared by mcm_konig_cover and mcm_bfs_levels: one complete BFS phase
+// (GPUBFS, no early exit) from the caller's matching, on workspace copies.
+static int64_t one_bfs_phase(Workspace &w, const Options &o, int32_t nc, int32_t nr, const int32_t *colptr,
+                             const int32_t *rowind, const int32_t *cm, const int32_t *rm, int32_t *clevel,
+                             hipStream_t st, DevGraph *gout)
+{
+    int64_t rc;
+    if ((rc = ensure_graph(w, (size_t)nc, (size_t)nr))) return rc;
+    DevGraph g;
+    g.colptr = colptr;
+    g.rowind = rowind;
+    g.nc = nc;
+    g.nr = nr;
+    g.cmatch = w.cwork;
+    g.rw = w.rw;
+    g.pred = w.pred;
+    g.cdone = w.cdone;
+    g.fq0 = w.fq;
+    g.fq1 = w.fq + nc;
+    g.ends = w.ends;
+    g.clevel = clevel;
+    uint32_t flags = F_NOAUG | (clevel ? F_LEVELS : 0u);
+    if (o.mapping != 0) flags |= F_WAVE;
+    HIPCHK(launch_setup(g, cm, rm, w.ctrl, flags, st));
+    int loop = 0;
+    Options oo = o;
+    if ((rc = run_graph(w, oo, g, flags, st, &loop))) return rc;
+    const int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
+    if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
+    *gout = g;
+    return 0;
+}
+
+int64_t mcm_konig_cover(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                        const int32_t *cmatch, const int32_t *rmatch, uint8_t *col_in_cover, uint8_t *row_in_cover,
+                        void *stream)
+{
+    int64_t rc;
+    if ((rc = check_graph_args(ncols, nrows, colptr, rowind))) return rc;
+    if ((ncols > 0 && (!cmatch || !col_in_cover)) || (nrows > 0 && (!rmatch || !row_in_cover)))
+        return fail(MCM_EINVAL, "NULL matching or cover array");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if ((rc = check_null_rowind(ncols, nrows, colptr, rowind, st))) return rc;
+    if (ncols == 0 || nrows == 0) {
+        if (ncols > 0) HIPCHK(hipMemsetAsync(col_in_cover, 0, ncols, st));
+        if (nrows > 0) HIPCHK(hipMemsetAsync(row_in_cover, 0, nrows, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return 0;
+    }
+    int dev = 0;
+    if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
+    const Options o = opts();
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[dev];
+    if ((rc = ensure_base(w, dev))) return rc;
+    DevGraph g;
+    if ((rc = one_bfs_phase(w, o, ncols, nrows, colptr, rowind, cmatch, rmatch, nullptr, st, &g))) return rc;
+    if (*ctrl_line(w.h_ctrl, L_NENDS) != 0) return fail(MCM_ENOTMAX, "the matching admits an augmenting path");
+    HIPCHK(launch_cover(g, 1, col_in_cover, row_in_cover, w.ctrl, st));
+    HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
+}
+
+int64_t mcm_bfs_levels(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                       const int32_t *cmatch, const int32_t *rmatch, int32_t *col_level, int32_t *row_pred, void *stream)
+{
+    int64_t rc;
+    if ((rc = check_graph_args(ncols, nrows, colptr, rowind))) return rc;
+    if ((ncols > 0 && (!cmatch || !col_level)) || (nrows > 0 && (!rmatch || !row_pred)))
+        return fail(MCM_EINVAL, "NULL matching or output array");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if ((rc = check_null_rowind(ncols, nrows, colptr, rowind, st))) return rc;
+    if (ncols == 0 || nrows == 0) {
+        // no edges: unmatched columns are level 0, nothing else is reached
+        if (nrows > 0) HIPCHK(hipMemsetAsync(row_pred, 0xff, sizeof(int32_t) * nrows, st));
+        if (ncols > 0) HIPCHK(hipMemsetAsync(col_level, 0, sizeof(int32_t) * ncols, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return 0;
+    }
+    int dev = 0;
+    if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
+    const Options o = opts();
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[dev];
+    if ((rc = ensure_base(w, dev))) return rc;
+    DevGraph g;
+    if ((rc = one_bfs_phase(w, o, ncols, nrows, colptr, rowind, cmatch, rmatch, col_level, st, &g))) return rc;
+    HIPCHK(launch_export_pred(g, 1, row_pred, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return (int64_t)*ctrl_line(w.h_ctrl, L_NENDS);
+}
+
+int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs, const int32_t *colptr_all,
+                          const int32_t *rowind_all, const int32_t *init_cmatch_all, const int32_t *init_rmatch_all,
+                          int32_t *out_cmatch_all, int32_t *out_rmatch_all, int64_t *out_card, void *stream)
+{
+    if (ngraphs < 0) return fail(MCM_EINVAL, "ngraphs < 0");
+    if (ngraphs == 0) return 0;
+    if (!graphs) return fail(MCM_EINVAL, "graphs is NULL");
+    if ((init_cmatch_all == nullptr) != (init_rmatch_all == nullptr))
+        return fail(MCM_EINVAL, "init arrays must both be NULL or both be given");
+    if (!colptr_all || !out_cmatch_all || !out_rmatch_all) return fail(MCM_EINVAL, "NULL packed array");
+    int64_t col_ext = 0, row_ext = 0;
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        const mcm_graph &d = graphs[i];
+        if (d.ncols < 0 || d.nrows < 0 || d.colptr_off < 0 || d.rowind_off < 0 || d.col_off < 0 || d.row_off < 0)
+            return fail(MCM_EINVAL, "graph %d: negative size or offset", i);
+        if (d.ncols > 0 && d.nrows > 0 && !rowind_all) return fail(MCM_EINVAL, "rowind_all is NULL");
+        col_ext = std::max(col_ext, d.col_off + d.ncols);
+        row_ext = std::max(row_ext, d.row_off + d.nrows);
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int dev = 0;
+    if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
+    const Options o = opts();
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[dev];
+    int64_t rc;
+    if ((rc = ensure_base(w, dev))) return rc;
+    if ((rc = ensure_graph(w, (size_t)std::max<int64_t>(col_ext, 1), (size_t)std::max<int64_t>(row_ext, 1)))) return rc;
+    if ((rc = ensure_desc(w, (size_t)ngraphs))) return rc;
+    // the frontier slices are 2*col_off .. 2*col_off + 2*nc: workspace fq holds 2*cap_nc entries
+    std::vector<int32_t> order(ngraphs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return (int64_t)graphs[a].ncols + graphs[a].nrows > (int64_t)graphs[b].ncols + graphs[b].nrows;
+    });
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        const mcm_graph &d = graphs[i];
+        w.h_desc[i] = BatchDesc{d.ncols, d.nrows, d.colptr_off, d.rowind_off, d.col_off, d.row_off};
+        w.h_order[i] = order[i];
+    }
+    HIPCHK(hipMemcpyAsync(w.desc, w.h_desc, sizeof(BatchDesc) * ngraphs, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.order, w.h_order, sizeof(int32_t) * ngraphs, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_zero_ctrl(w.ctrl, st));
+    uint32_t flags = base_flags(o, 0, 0);
+    RunOpt ro = run_opt(o, flags, std::max<int64_t>(col_ext, 1), w.info);
+    int blocks = std::min<int64_t>(ngraphs, (int64_t)w.info.ncu * 4);
+    HIPCHK(hipEventRecord(w.ev0, st));
+    HIPCHK(launch_match_wg(w.desc, w.order, ngraphs, colptr_all, rowind_all, init_cmatch_all, init_rmatch_all,
+                           out_cmatch_all, out_rmatch_all, w.rw, w.pred, w.cdone, w.fq, w.ends, w.card, w.ctrl, ro,
+                           (flags & F_WAVE) != 0, blocks, o.wg_block, st));
+    HIPCHK(hipEventRecord(w.ev1, st));
+    HIPCHK(hipMemcpyAsync(w.h_card, w.card, sizeof(int64_t) * ngraphs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, w.ev0, w.ev1));
+    int64_t total = 0;
+    bool bad = false;
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        if (w.h_card[i] < 0) bad = true;
+        else total += w.h_card[i];
+        if (out_card) out_card[i] = w.h_card[i];
+    }
+    record_stats(w.h_ctrl, -1, total, ms, 2, flags);
+    const int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
+    if (bad || s != 0) return fail(MCM_EINTERNAL, "device watchdog fired in a batched graph (status %d)", s);
+    return total;
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Internal layout shared by the host driver and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+namespace mcm {
+
+// Control block: every field the kernels update concurrently sits on its
+// own 128-byte line so that atomics on one do not contend with polls of
+// another.
+enum CtrlLine : int {
+    L_BAR_COUNT = 0,   // grid barrier arrivals
+    L_BAR_GEN,         // grid barrier generation
+    L_FCOUNT0,         // frontier sizes, rotating over three levels
+    L_FCOUNT1,
+    L_FCOUNT2,
+    L_FOUND0,          // "this level reached an unmatched row", rotating
+    L_FOUND1,
+    L_FOUND2,
+    L_NENDS,           // unmatched rows reached in this phase
+    L_STATUS,          // 0, or a negative mcm_status set by a device watchdog
+    L_PHASE,           // phases run (== stamp of the last phase)
+    L_LEVELS,          // BFS levels expanded, all phases
+    L_CARD,            // |M| (64-bit)
+    L_STAT0,           // stats counters (64-bit each, own lines)
+    L_NLINES = L_STAT0 + 8
+};
+constexpr int kLineWords = 32;  // 128 B / 4 B
+
+enum StatIdx : int {
+    S_EDGES = 0, S_EXPANDED, S_CLAIMED, S_FOUND, S_ALT, S_FIX, S_BATCH_LEVELS, S_SPARE
+};
+
+enum Flags : uint32_t {
+    F_WR = 1u,        // GPUBFS-WR early exit (Algorithm 4)
+    F_APSB = 2u,      // stop the level loop at the first level that finds a row
+    F_STATS = 4u,     // count edges, claims, ...
+    F_LEVELS = 8u,    // record column levels (inspection mode)
+    F_NOAUG = 16u,    // one BFS phase only, no Alternate/Fix (levels, cover)
+    F_WAVE = 32u      // wave-balanced edge mapping (else one column per lane)
+};
+
+// Device view of one graph plus its working state.
+struct DevGraph {
+    const int32_t *colptr;   // [nc+1]
+    const int32_t *rowind;   // [nnz]
+    int32_t nc, nr;
+    int32_t *cmatch;         // [nc]   column -> row (the output array)
+    uint64_t *rw;            // [nr]   row word: low 32 = rmatch, high 32 = visit stamp
+    int32_t *pred;           // [nr]   BFS predecessor column of a reached row
+    uint32_t *cdone;         // [nc]   stamp of the phase in which root c found a row
+    int4 *fq0, *fq1;         // [nc]   frontier queues {col, root, beg, end}
+    int32_t *ends;           // [nr]   unmatched rows reached this phase
+    int32_t *clevel;         // [nc]   column levels (F_LEVELS) or null
+};
+
+// Options of one run, passed by value to the kernels.
+struct RunOpt {
+    uint32_t flags;        // Flags
+    uint32_t max_phases;   // watchdog: phases
+    uint32_t max_levels;   // watchdog: levels per phase
+    uint64_t timeout;      // wall-clock ticks a grid barrier may wait
+};
+
+// One graph of a batch (same fields as mcm_graph of the C interface).
+struct BatchDesc {
+    int32_t nc, nr;
+    int64_t colptr_off, rowind_off, col_off, row_off;
+};
+
+}  // namespace mcm

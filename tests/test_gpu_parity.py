@@ -1,0 +1,301 @@
+"""GPU path vs the CPU oracle, through the C ABI.
+
+Cardinality must equal the oracle's exactly; the returned arrays must form a
+matching of the input; maximality is certified by a Konig cover exported by
+the GPU and checked by the oracle's independent verifier.  The matching
+arrays themselves are not compared: maximum matchings are not unique and the
+GPU's depends on the schedule of the concurrent flips."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_1303_1379_amd import graphgen as gg, mcm  # noqa: E402
+from conftest import load_golden  # noqa: E402
+
+DRIVER_COMBOS = [
+    dict(driver="apfb", bfs="wr", mapping="wave", loop="device"),
+    dict(driver="apfb", bfs="wr", mapping="thread", loop="device"),
+    dict(driver="apfb", bfs="plain", mapping="wave", loop="device"),
+    dict(driver="apsb", bfs="wr", mapping="wave", loop="device"),
+    dict(driver="apsb", bfs="plain", mapping="thread", loop="device"),
+    dict(driver="apfb", bfs="wr", mapping="wave", loop="host"),
+    dict(driver="apsb", bfs="wr", mapping="thread", loop="host"),
+]
+
+DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384)
+
+
+@pytest.fixture(autouse=True)
+def _reset_options():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    for k, v in DEFAULTS.items():
+        mcm.set_option(k, v)
+    yield
+    for k, v in DEFAULTS.items():
+        mcm.set_option(k, v)
+
+
+def _set(**kw):
+    for k, v in kw.items():
+        mcm.set_option(k, v)
+
+
+def _oracle_card(g, init="cheap"):
+    if init == "cheap":
+        cm, rm = O.cheap_init(g)
+    else:
+        cm, rm = np.full(g.nc, -1, np.int32), np.full(g.nr, -1, np.int32)
+    return O.hopcroft_karp(g, cm, rm)[0]
+
+
+def _gpu(g, init="cheap", certify=True):
+    dg = mcm.to_device(g)
+    if init == "cheap":
+        _, cm0, rm0 = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)
+        card, cm, rm = mcm.match(dg, torch.from_numpy(cm0).cuda(), torch.from_numpy(rm0).cuda())
+    else:
+        card, cm, rm = mcm.match(dg)
+    cmh, rmh = cm.cpu().numpy(), rm.cpu().numpy()
+    assert O.check_matching(g, cmh, rmh) == card, f"{g.name}: not a matching of size {card}"
+    if certify:
+        k, cc, rc = mcm.konig_cover(dg, cm, rm)
+        assert k == card
+        assert O.verify_cover(g, cmh, rmh, cc.cpu().numpy(), rc.cpu().numpy()) == 0
+    return card, cmh, rmh
+
+
+# ------------------------------------------------------------------ the paper's Fig. 1
+def test_fig1_worked_example():
+    d = load_golden("fig1.txt")
+    g = gg.from_edges(d["nc"], d["nr"], d["edges"])
+    cm = np.full(g.nc, -1, np.int32)
+    rm = np.full(g.nr, -1, np.int32)
+    for c, r in d["match"]:
+        cm[c], rm[r] = r, c
+    dg = mcm.to_device(g)
+    cmt, rmt = torch.from_numpy(cm).cuda(), torch.from_numpy(rm).cuda()
+    nfree, cl, rp = mcm.bfs_levels(dg, cmt, rmt)
+    assert nfree == d["expect_free_reached"]
+    assert cl.cpu().tolist() == d["expect_clevel"]
+    # r2 and r3 are both reached from c2 (the second walk must stop at c2)
+    assert rp.cpu().tolist() == [0, 1, 1]
+    for combo in DRIVER_COMBOS:
+        for thr in (16384, 0):
+            _set(wg_threshold=thr, **combo)
+            card, cmo, rmo = mcm.match(dg, cmt.clone(), rmt.clone())
+            assert card == d["expect_card"], (combo, thr)
+            assert O.check_matching(g, cmo.cpu().numpy(), rmo.cpu().numpy()) == card
+
+
+# ------------------------------------------------------------------ tiny graphs, every path
+@pytest.mark.parametrize("path", ["wg", "device", "host"])
+def test_random_tiny_graphs(path):
+    rng = np.random.default_rng(7)
+    if path == "wg":
+        _set(wg_threshold=1 << 30)
+    else:
+        _set(wg_threshold=0, loop=path)
+    for i in range(60):
+        nc, nr = int(rng.integers(1, 14)), int(rng.integers(1, 14))
+        g = gg.random_small(nc, nr, float(rng.choice([0.1, 0.25, 0.5])), 100 + i)
+        bf = O.brute_force(g)
+        for init in ("cheap", "empty"):
+            card, _, _ = _gpu(g, init)
+            assert card == bf, (path, i, init)
+
+
+# ------------------------------------------------------------------ closed forms and edge cases
+@pytest.mark.parametrize("thr", [1 << 30, 0])
+def test_closed_forms(thr):
+    _set(wg_threshold=thr)
+    assert _gpu(gg.complete(7, 5))[0] == 5
+    assert _gpu(gg.complete(5, 9), "empty")[0] == 5
+    assert _gpu(gg.star(30))[0] == 1
+    for k in (2, 7, 64, 513):
+        assert _gpu(gg.path(k), "empty")[0] == k // 2
+    assert _gpu(gg.permutation_plus_noise(3000, 3, 4))[0] == 3000
+    assert _gpu(gg.grid5(64, 0, 0, 1), "empty")[0] == 64 * 64
+    assert _gpu(gg.grid5(64, 200, 0, 3))[0] == 64 * 64 - 200
+
+
+def test_empty_inputs():
+    for nc, nr in [(0, 0), (0, 5), (5, 0), (6, 4)]:
+        g = gg.empty(nc, nr)
+        dg = mcm.to_device(g)
+        card, cm, rm = mcm.match(dg)
+        assert card == 0
+        assert (cm.cpu().numpy() == -1).all() and (rm.cpu().numpy() == -1).all()
+        k, cc, rc = mcm.konig_cover(dg, cm, rm)
+        assert k == 0
+
+
+def test_outputs_may_alias_init():
+    g = gg.workload("grid64")
+    _, cm0, rm0 = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)
+    dg = mcm.to_device(g)
+    for thr in (1 << 30, 0):
+        _set(wg_threshold=thr)
+        cm = torch.from_numpy(cm0).cuda()
+        rm = torch.from_numpy(rm0).cuda()
+        card, cmo, rmo = mcm.match(dg, cm, rm, out_cmatch=cm, out_rmatch=rm)
+        assert cmo.data_ptr() == cm.data_ptr()
+        assert card == _oracle_card(g)
+        assert O.check_matching(g, cm.cpu().numpy(), rm.cpu().numpy()) == card
+
+
+def test_maximum_init_is_kept():
+    g = gg.workload("uniform2000")
+    card, cm, rm, _ = O.hopcroft_karp(g, *O.cheap_init(g))
+    dg = mcm.to_device(g)
+    c2, cmo, rmo = mcm.match(dg, torch.from_numpy(cm).cuda(), torch.from_numpy(rm).cuda())
+    assert c2 == card
+    assert mcm.last_stats()["phases"] == 1
+
+
+# ------------------------------------------------------------------ level sets of one BFS (GPUBFS mode)
+@pytest.mark.parametrize("name", ["uniform2000", "grid96", "rmat12"])
+@pytest.mark.parametrize("mapping", ["wave", "thread"])
+@pytest.mark.parametrize("loop", ["device", "host"])
+def test_bfs_levels_exact(name, mapping, loop):
+    _set(mapping=mapping, loop=loop)
+    g = gg.workload(name)
+    cm, rm = O.cheap_init(g)
+    ocl, orl, ofree = O.alt_bfs_levels(g, cm, rm)
+    dg = mcm.to_device(g)
+    nfree, cl, rp = mcm.bfs_levels(dg, torch.from_numpy(cm).cuda(), torch.from_numpy(rm).cuda())
+    cl, rp = cl.cpu().numpy(), rp.cpu().numpy()
+    assert nfree == ofree
+    assert (cl == ocl).all()
+    reached = rp >= 0
+    assert (reached == (orl >= 0)).all()
+    # pred[r] is a column adjacent to r at the level that reaches r
+    rows = np.flatnonzero(reached)
+    pc = rp[rows]
+    assert (cl[pc] == orl[rows]).all()
+    for r, c in zip(rows[:4000], pc[:4000]):
+        assert r in g.rowind[g.colptr[c]:g.colptr[c + 1]]
+
+
+# ------------------------------------------------------------------ driver variants
+@pytest.mark.parametrize("combo", DRIVER_COMBOS, ids=lambda c: "-".join(c.values()))
+@pytest.mark.parametrize("name", ["uniform2000", "grid128", "rmat13"])
+def test_driver_variants(combo, name):
+    g = gg.workload(name)
+    ref = _oracle_card(g)
+    for thr in (1 << 30, 0):
+        _set(wg_threshold=thr, **combo)
+        card, _, _ = _gpu(g)
+        assert card == ref, (combo, thr)
+
+
+@pytest.mark.parametrize("name,init", [("grid256", "cheap"), ("grid200", "empty"), ("rmat15", "cheap"),
+                                       ("rmat14", "empty")])
+def test_medium_graphs(name, init):
+    g = gg.workload(name)
+    card, _, _ = _gpu(g, init)
+    assert card == _oracle_card(g, init)
+
+
+def test_uneven_and_rectangular():
+    for nc, nr, d, s in [(5000, 800, 3, 1), (800, 5000, 6, 2), (20000, 20000, 2, 3), (40000, 9000, 1, 4)]:
+        g = gg.uniform(nc, nr, d, s)
+        assert _gpu(g)[0] == _oracle_card(g)
+        assert _gpu(g, "empty")[0] == _oracle_card(g, "empty")
+
+
+def test_validation_errors():
+    _set(validate=1)
+    g = gg.workload("grid64")
+    dg = mcm.to_device(g)
+    _, cm0, rm0 = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)
+    bad_c = cm0.copy()
+    c = int(np.flatnonzero(bad_c >= 0)[0])
+    bad_c[c] = (bad_c[c] + 7) % g.nr            # no longer symmetric
+    with pytest.raises(mcm.McmError) as e:
+        mcm.match(dg, torch.from_numpy(bad_c).cuda(), torch.from_numpy(rm0).cuda())
+    assert e.value.code == mcm.MCM_EBADINIT
+    bad_ri = g.rowind.copy()
+    bad_ri[5] = g.nr + 3                         # row out of range
+    dgb = mcm.DeviceGraph(g.nc, g.nr, dg.colptr, torch.from_numpy(bad_ri).cuda())
+    with pytest.raises(mcm.McmError) as e:
+        mcm.match(dgb)
+    assert e.value.code == mcm.MCM_EINVAL
+    # the valid input still passes with validation on
+    assert mcm.match(dg, torch.from_numpy(cm0).cuda(), torch.from_numpy(rm0).cuda())[0] == _oracle_card(g)
+
+
+def test_cover_rejects_non_maximum():
+    g = gg.workload("grid64")
+    _, cm0, rm0 = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)
+    if (cm0 >= 0).sum() == _oracle_card(g):
+        pytest.skip("greedy already maximum")
+    dg = mcm.to_device(g)
+    with pytest.raises(mcm.McmError) as e:
+        mcm.konig_cover(dg, torch.from_numpy(cm0).cuda(), torch.from_numpy(rm0).cuda())
+    assert e.value.code == mcm.MCM_ENOTMAX
+
+
+def test_stats_counters():
+    _set(stats=1, wg_threshold=0)
+    g = gg.workload("rmat13")
+    card, _, _ = _gpu(g, certify=False)
+    s = mcm.last_stats()
+    assert s["card"] == card and s["phases"] >= 2 and s["levels"] >= s["phases"]
+    assert s["edges_scanned"] > 0 and s["rows_found"] >= card - int((O.cheap_init(g)[0] >= 0).sum())
+
+
+# ------------------------------------------------------------------ batched
+def _batch_graphs(n, hi=4096):
+    return [gg.batch_member(4, i, hi=hi) for i in range(n)]
+
+
+@pytest.mark.parametrize("mapping", ["wave", "thread"])
+def test_batched_equals_oracle_and_single(mapping):
+    _set(mapping=mapping)
+    graphs = _batch_graphs(300)
+    inits = [mcm.cheap_init_host(g.colptr, g.rowind, g.nr) for g in graphs]
+    b = mcm.pack_batch(graphs)
+    icm = torch.from_numpy(np.concatenate([x[1] for x in inits])).cuda()
+    irm = torch.from_numpy(np.concatenate([x[2] for x in inits])).cuda()
+    total, cards, cm, rm = mcm.match_batched(b, icm, irm)
+    cmh, rmh = cm.cpu().numpy(), rm.cpu().numpy()
+    co = ro = 0
+    for i, g in enumerate(graphs):
+        ref = _oracle_card(g)
+        assert cards[i] == ref, i
+        assert O.check_matching(g, cmh[co:co + g.nc], rmh[ro:ro + g.nr]) == ref
+        co += g.nc
+        ro += g.nr
+    assert total == cards.sum()
+    # equal to per-graph mcm_match
+    for i in range(0, 300, 37):
+        g = graphs[i]
+        assert _gpu(g, certify=False)[0] == cards[i]
+
+
+def test_batched_empty_members_and_no_init():
+    graphs = [gg.empty(0, 0), gg.complete(3, 4), gg.empty(5, 0), gg.path(9), gg.empty(0, 3), gg.star(6)]
+    b = mcm.pack_batch(graphs)
+    total, cards, cm, rm = mcm.match_batched(b)
+    assert cards.tolist() == [0, 3, 0, 4, 0, 1]
+    assert total == 8
+
+
+# ------------------------------------------------------------------ full-size workloads (as timed by bench.py)
+@pytest.mark.parametrize("name", ["grid2048", "rmat23"])
+def test_full_size_certified(name):
+    """Full size: oracle-free exact certificate.  The output must be a valid
+    matching and the GPU's Konig cover (checked by the oracle's verifier)
+    proves it maximum by weak duality; for the grid the size must also lie in
+    the closed-form window n - |Rdel u Cdel| <= nu <= n - ndel."""
+    g = gg.workload(name)
+    card, cm, rm = _gpu(g)
+    if name == "grid2048":
+        n = 2048 * 2048
+        nd = int(np.floor(0.03 * n))
+        _, dc, dr = gg.grid5(2048, nd, nd, 2, return_masks=True)
+        assert n - int((dc | dr).sum()) <= card <= n - nd
