@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: maximum-cardinality matching on one MI355X through libmcm.
+
+One step = one mcm_match call on the workload (copy of the greedy initial
+matching into the working state, all phases of APFB with GPUBFS-WR,
+Alternate and FixMatching, unpack and count, stream synchronised), with the
+graph and the initial matching already resident in HBM.
+
+Prints ONE JSON line.  `value` is edges scanned per second (scanned edges
+of the step counted by the library's device counters in an untimed run,
+divided by the measured time per step).  `roofline` relates the algorithmic
+bytes of the persistent matching kernel (fixed per-unit byte model: 8 B per
+scanned edge, 16 B per expanded and per claimed column, 12 B per unmatched
+row found, 20 B per Alternate step, per phase 4 B per column read by the
+root scan, nc/8 B of visit reset and 8 B per row read by FixMatching, 4 B per
+root) to its average duration from HIP events over the timed steps.
+`cpu_baseline` is the CPU oracle (Hopcroft-Karp, one thread) timed on a
+bounded sample of the same input.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Matching time & edges scanned/s (%HBM peak); batched graphs/s vs per-graph loop"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "grid2048": "5-point grid pattern on a 2048x2048 grid (4,194,304 rows and columns), 3% of columns and "
+                "3% of rows emptied at random (seed 2), int32 CSC, greedy initial matching",
+    "rmat23": "R-MAT (a=.57, b=.19, c=.19, d=.05), 2^23 rows x 2^23 columns, 16 samples per column, duplicates "
+              "removed, random row/column permutation (seed 3), int32 CSC, greedy initial matching",
+    "uniform2000": "2000 x 2000 uniform random bipartite graph, 4 row draws per column (seed 1), duplicates "
+                   "removed, int32 CSC, greedy initial matching",
+}
+
+
+def alg_bytes(s, nc, nr):
+    """Algorithmic bytes of one match from its device counters (see module doc)."""
+    per_phase = 4 * nc + nc / 8 + 8 * nr
+    return (8 * s["edges_scanned"] + 16 * s["cols_expanded"] + 16 * s["cols_claimed"] + 12 * s["rows_found"]
+            + 20 * s["alt_steps"] + 4 * s["roots"] + s["phases"] * per_phase)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("mcm_kernels.hip", "mcm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1303_1379_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, per_launch_check):
+    """HBM bytes per launch of the persistent kernel from the committed
+    rocprofv3 counter summary, or None when missing or taken on other
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_persistent_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(g, cm0, rm0, budget_s):
+    import oracle
+    s = oracle.hopcroft_karp_sample(g, cm0, rm0, budget_s)
+    rate = s["edges"] / s["seconds"] if s["seconds"] > 0 else None
+    what = "complete run" if s["done"] else f"first {s['phases']} phases"
+    return {"value": rate, "unit": "edges scanned/s", "cores": 1, "kind": "oracle",
+            "sample": f"Hopcroft-Karp (single thread) on the same input from the same greedy matching, {what}: "
+                      f"{s['edges']} edges scanned in {s['seconds']:.2f} s",
+            "phases": s["phases"], "seconds": round(s["seconds"], 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="grid2048", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--no-stats", action="store_true", help="skip the untimed counter run")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of matching, copy this many bytes with a plain device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(graphs shard by independent batches across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1303_1379_amd import graphgen as gg, mcm
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    if args.copy_bytes:
+        n = args.copy_bytes // 4
+        a = torch.ones(n, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(args.warmup + args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4, "launches": args.warmup + args.steps}))
+        return
+
+    t0 = time.time()
+    g = gg.workload(args.workload)
+    t_gen = time.time() - t0
+    init_card, cm0, rm0 = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)
+    dg = mcm.to_device(g, dev)
+    icm = torch.from_numpy(cm0).to(dev)
+    irm = torch.from_numpy(rm0).to(dev)
+    ocm = torch.empty_like(icm)
+    orm = torch.empty_like(irm)
+    mcm.set_option("stats", 0)
+
+    # counters of one match (untimed)
+    stats = None
+    if not args.no_stats:
+        mcm.set_option("stats", 1)
+        mcm.match(dg, icm, irm, ocm, orm)
+        stats = mcm.last_stats()
+        mcm.set_option("stats", 0)
+
+    for _ in range(args.warmup):
+        mcm.match(dg, icm, irm, ocm, orm)
+    torch.cuda.synchronize()
+    kernel_ms = []
+    cards = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        card, _, _ = mcm.match(dg, icm, irm, ocm, orm)
+        kernel_ms.append(mcm.last_stats()["kernel_ms"])
+        cards.append(card)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    ms_per_step = (t_end - t_start) * 1000.0 / args.steps
+    last = mcm.last_stats()
+    assert len(set(cards)) == 1, f"cardinality varied across steps: {cards}"
+
+    out = {
+        "metric": METRIC,
+        "value": None,
+        "unit": "edges scanned/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "ncols": g.nc, "nrows": g.nr,
+                   "nnz": g.nnz, "input_fnv1a": hex(g.fnv1a()), "driver": mcm.get_option("driver"),
+                   "bfs": mcm.get_option("bfs"), "mapping": mcm.get_option("mapping"),
+                   "loop": mcm.get_option("loop")},
+        "card": cards[0],
+        "init_card": int(init_card),
+        "matching_ms_median": round(float(np.median(kernel_ms)), 4),
+        "graph_teps": round(g.nnz / (ms_per_step / 1000.0), 1),
+    }
+    if stats is not None:
+        edges = stats["edges_scanned"]
+        out["value"] = round(edges / (ms_per_step / 1000.0), 1)
+        out["phases"] = stats["phases"]
+        out["levels"] = stats["levels"]
+        out["edges_scanned_per_step"] = edges
+        b = alg_bytes(stats, g.nc, g.nr)
+        avg_k = float(np.mean(kernel_ms)) / 1000.0
+        achieved = b / avg_k / 1e9
+        traffic = load_traffic(args.workload, b)
+        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                           "kernel": "k_persistent<true>", "alg_bytes_per_launch": int(b),
+                           "avg_launch_ms": round(avg_k * 1000.0, 4)}
+        out["block0_ms"] = {k: round(stats[k], 2) for k in ("t_expand_ms", "t_flush_ms", "t_barrier_ms",
+                                                             "t_small_ms", "t_augment_ms")}
+    out["setup_s"] = {"generate": round(t_gen, 2)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(g, cm0, rm0, args.cpu_budget)
+        out["cpu_baseline"]["cores"] = 1
+        out["cpu_baseline"]["host_cpus"] = os.cpu_count()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

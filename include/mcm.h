@@ -201,6 +201,12 @@ typedef struct {
     int64_t rows_found;      /* unmatched rows reached, summed over phases (stats=1) */
     int64_t alt_steps;       /* Alternate loop iterations (stats=1) */
     int64_t fix_resets;      /* rows reset by FixMatching (stats=1) */
+    int64_t roots;           /* frontier roots enqueued, summed over phases (stats=1) */
+    double  t_expand_ms;     /* block 0 of the persistent launch (stats=1): expanding levels, */
+    double  t_flush_ms;      /*   handing staged queue entries over, */
+    double  t_barrier_ms;    /*   waiting in grid barriers, */
+    double  t_small_ms;      /*   running single-workgroup levels, */
+    double  t_augment_ms;    /*   in Alternate and FixMatching */
     int64_t init_card;       /* |M| of the initial matching */
     int64_t card;            /* |M| returned */
     double  kernel_ms;       /* device time of the matching, HIP events */

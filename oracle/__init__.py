@@ -56,6 +56,8 @@ def _load():
         lib.orc_cheap_init.restype = None
         lib.orc_hopcroft_karp.argtypes = [i32, i32, vp, vp, vp, vp, vp]
         lib.orc_hopcroft_karp.restype = ctypes.c_int64
+        lib.orc_hopcroft_karp_ex.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.c_int64, vp, vp]
+        lib.orc_hopcroft_karp_ex.restype = ctypes.c_int64
         lib.orc_konig_cover.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
         lib.orc_konig_cover.restype = ctypes.c_int64
         lib.orc_verify_cover.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
@@ -123,6 +125,33 @@ def hopcroft_karp(g, cmatch=None, rmatch=None, timed: bool = False):
         raise MemoryError("orc_hopcroft_karp failed")
     out = (int(card), cm[:nc].copy(), rm[:nr].copy(), int(ph.value))
     return out + (dt,) if timed else out
+
+
+def hopcroft_karp_sample(g, cmatch, rmatch, budget_s: float = 15.0):
+    """Bounded CPU sample: Hopcroft-Karp phases, one call per phase, from
+    (cmatch, rmatch) until `budget_s` seconds of phase time have been spent
+    or the matching is maximum.  Returns dict(seconds, phases, edges, card,
+    done).  Single thread."""
+    nc, nr, cp, ri = _g(g)
+    cm = np.full(max(nc, 1), -1, np.int32)
+    rm = np.full(max(nr, 1), -1, np.int32)
+    cm[:nc] = cmatch
+    rm[:nr] = rmatch
+    lib = _load()
+    total_t, total_e, total_p, done, card = 0.0, 0, 0, False, int((cm[:nc] >= 0).sum())
+    while total_t < budget_s:
+        ph = ctypes.c_int64(0)
+        ed = ctypes.c_int64(0)
+        t0 = time.perf_counter()
+        card = lib.orc_hopcroft_karp_ex(nc, nr, cp.ctypes.data, ri.ctypes.data, cm.ctypes.data, rm.ctypes.data, 1,
+                                        ctypes.addressof(ph), ctypes.addressof(ed))
+        total_t += time.perf_counter() - t0
+        total_e += int(ed.value)
+        if ph.value == 0:
+            done = True
+            break
+        total_p += int(ph.value)
+    return {"seconds": total_t, "phases": total_p, "edges": total_e, "card": int(card), "done": done}
 
 
 def konig_cover(g, cmatch, rmatch):

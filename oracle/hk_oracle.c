@@ -114,10 +114,25 @@ void orc_cheap_init(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t
  * Stops when the BFS reaches no unmatched row.  Returns |M|; the number of
  * phases that augmented is stored in *phases.
  */
+int64_t orc_hopcroft_karp_ex(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind,
+                             int32_t *cmatch, int32_t *rmatch, int64_t max_phases, int64_t *phases,
+                             int64_t *edges_scanned);
+
 int64_t orc_hopcroft_karp(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind,
                           int32_t *cmatch, int32_t *rmatch, int64_t *phases)
 {
+    return orc_hopcroft_karp_ex(nc, nr, colptr, rowind, cmatch, rmatch, INT64_MAX, phases, NULL);
+}
+
+/* Same, stopping after at most max_phases augmenting phases (the matching
+ * is then valid but possibly not maximum); *edges_scanned (if non-NULL)
+ * receives the number of adjacency entries read by the BFS and DFS steps. */
+int64_t orc_hopcroft_karp_ex(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind,
+                             int32_t *cmatch, int32_t *rmatch, int64_t max_phases, int64_t *phases,
+                             int64_t *edges_scanned)
+{
     (void)nr;
+    int64_t nedges = 0;
     int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc + 1));
     int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc + 1));
     int64_t *it = (int64_t *)malloc(sizeof(int64_t) * ((size_t)nc + 1));
@@ -138,6 +153,7 @@ int64_t orc_hopcroft_karp(int32_t nc, int32_t nr, const int32_t *colptr, const i
         while (qh < qt) {
             int32_t c = queue[qh++];
             if (dist[c] >= limit) continue;
+            nedges += colptr[c + 1] - colptr[c];
             for (int64_t j = colptr[c]; j < colptr[c + 1]; ++j) {
                 int32_t r = rowind[j];
                 int32_t m = rmatch[r];
@@ -166,6 +182,7 @@ int64_t orc_hopcroft_karp(int32_t nc, int32_t nr, const int32_t *colptr, const i
                     continue;
                 }
                 int32_t r = rowind[it[u]++];
+                ++nedges;
                 int32_t m = rmatch[r];
                 if (m == -1) {
                     if (dist[u] + 1 != limit) continue;
@@ -188,10 +205,12 @@ int64_t orc_hopcroft_karp(int32_t nc, int32_t nr, const int32_t *colptr, const i
         }
         ++nph;
         if (augmented == 0) break; /* cannot happen when limit < INF; kept as a guard */
+        if (nph >= max_phases) break;
     }
     int64_t card = 0;
     for (int32_t c = 0; c < nc; ++c) card += (cmatch[c] >= 0);
     if (phases) *phases = nph;
+    if (edges_scanned) *edges_scanned = nedges;
     free(dist); free(queue); free(it); free(stack);
     return card;
 }

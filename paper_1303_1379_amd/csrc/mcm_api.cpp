@@ -21,11 +21,11 @@
 #include "mcm_internal.h"
 
 namespace mcm {
-hipError_t launch_setup(const DevGraph &, const int32_t *, const int32_t *, uint32_t *, uint32_t, hipStream_t);
+hipError_t launch_setup(const DevGraph &, const int32_t *, const int32_t *, uint32_t *, uint32_t *, uint32_t, hipStream_t);
 hipError_t launch_validate(int32_t, int32_t, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
                            uint32_t *, hipStream_t);
 hipError_t persistent_occupancy(bool, int, int *);
-hipError_t launch_persistent(const DevGraph &, uint32_t *, const RunOpt &, bool, int, int, hipStream_t);
+hipError_t launch_persistent(const DevGraph &, uint32_t *, uint32_t *, const RunOpt &, bool, int, int, hipStream_t);
 hipError_t launch_init_roots(const DevGraph &, uint32_t *, uint32_t, hipStream_t);
 hipError_t launch_level(const DevGraph &, uint32_t *, uint32_t, uint32_t, int, uint32_t, bool, int, hipStream_t);
 hipError_t launch_alternate(const DevGraph &, uint32_t *, uint32_t, uint32_t, hipStream_t);
@@ -77,6 +77,7 @@ struct Options {
     int blocks_per_cu = 1;    // 0 = occupancy limit
     int wg_block = 512;       // one-workgroup matcher block size
     int64_t wg_threshold = 16384;  // nc + nr at or below which one workgroup matches alone
+    int64_t small_max = 256;  // frontiers up to this size are expanded by one workgroup
     double timeout_s = 20.0;  // device barrier wait limit
 };
 Options g_opt;
@@ -104,6 +105,7 @@ struct Workspace {
     int32_t *ends = nullptr;
     int32_t *cwork = nullptr;
     uint32_t *ctrl = nullptr;
+    uint32_t *bar = nullptr;     // grid barrier arrival flags
     BatchDesc *desc = nullptr;
     size_t cap_desc = 0;
     int32_t *order = nullptr;
@@ -138,6 +140,7 @@ int64_t ensure_base(Workspace &w, int dev)
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate > 0)
         w.info.clock_khz = rate;
     HIPCHK(hipMalloc(&w.ctrl, (size_t)L_NLINES * 128));
+    HIPCHK(hipMalloc(&w.bar, (size_t)kMaxGridBlocks * 128));
     HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&w.h_ctrl), (size_t)L_NLINES * 128, hipHostMallocDefault));
     HIPCHK(hipEventCreate(&w.ev0));
     HIPCHK(hipEventCreate(&w.ev1));
@@ -204,6 +207,7 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     r.flags = flags;
     r.max_phases = (uint32_t)std::min<int64_t>(nc + 2, 0x7fffffff);
     r.max_levels = (uint32_t)std::min<int64_t>(nc + 2, 0x7fffffff);
+    r.small_max = (uint32_t)o.small_max;
     r.timeout = (uint64_t)(o.timeout_s * info.clock_khz * 1000.0);
     return r;
 }
@@ -224,7 +228,10 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
         if (occ < 1) return fail(MCM_EHIP, "persistent kernel cannot be resident with block %d", o.block);
         int per_cu = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
         int blocks = w.info.ncu * per_cu;
-        HIPCHK(launch_persistent(g, w.ctrl, ro, wave, blocks, o.block, st));
+        HIPCHK(hipEventRecord(w.ev0, st));
+        if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+        HIPCHK(launch_persistent(g, w.ctrl, w.bar, ro, wave, blocks, o.block, st));
+        HIPCHK(hipEventRecord(w.ev1, st));
         HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         return 0;
@@ -238,6 +245,7 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
     };
     uint32_t phases = 0, levels = 0;
     int64_t rc;
+    HIPCHK(hipEventRecord(w.ev0, st));
     for (uint32_t ph = 1;; ++ph) {
         if (ph > ro.max_phases) return fail(MCM_EINTERNAL, "phase bound exceeded");
         HIPCHK(launch_init_roots(g, w.ctrl, flags, st));
@@ -259,6 +267,7 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
         HIPCHK(launch_alternate(g, w.ctrl, ne, flags, st));
         HIPCHK(launch_fix(g, w.ctrl, flags, st));
     }
+    HIPCHK(hipEventRecord(w.ev1, st));
     // record counts in the device control block so both loops report alike
     hc[L_PHASE * kLineWords] = phases;
     hc[L_LEVELS * kLineWords] = levels;
@@ -286,7 +295,8 @@ int current_device(int *dev)
     return hipGetDevice(dev) == hipSuccess ? 0 : -1;
 }
 
-void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int loop, uint32_t flags)
+void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int loop, uint32_t flags,
+                  double clock_khz = 100000.0)
 {
     std::lock_guard<std::mutex> lk(g_stats_mu);
     mcm_stats s{};
@@ -298,6 +308,12 @@ void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int l
     s.rows_found = (int64_t)ctrl_stat(hc, S_FOUND);
     s.alt_steps = (int64_t)ctrl_stat(hc, S_ALT);
     s.fix_resets = (int64_t)ctrl_stat(hc, S_FIX);
+    s.roots = (int64_t)ctrl_stat(hc, S_ROOTS);
+    s.t_expand_ms = (double)ctrl_stat(hc, S_T_EXPAND) / clock_khz;
+    s.t_flush_ms = (double)ctrl_stat(hc, S_T_FLUSH) / clock_khz;
+    s.t_barrier_ms = (double)ctrl_stat(hc, S_T_BARRIER) / clock_khz;
+    s.t_small_ms = (double)ctrl_stat(hc, S_T_SMALL) / clock_khz;
+    s.t_augment_ms = (double)ctrl_stat(hc, S_T_AUGMENT) / clock_khz;
     s.init_card = init_card;
     s.card = card;
     s.kernel_ms = ms;
@@ -419,6 +435,9 @@ int mcm_set_option(const char *key, const char *value)
     } else if (k == "wg_threshold") {
         if (!as_int(0, (int64_t)1 << 40, &x)) return (int)fail(MCM_EINVAL, "wg_threshold must be >= 0");
         g_opt.wg_threshold = x;
+    } else if (k == "small_max") {
+        if (!as_int(0, (int64_t)1 << 30, &x)) return (int)fail(MCM_EINVAL, "small_max must be in [0, 2^30]");
+        g_opt.small_max = x;
     } else if (k == "timeout_s") {
         char *end = nullptr;
         double d = strtod(value, &end);
@@ -448,6 +467,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "blocks_per_cu") v = std::to_string(o.blocks_per_cu);
     else if (k == "wg_block") v = std::to_string(o.wg_block);
     else if (k == "wg_threshold") v = std::to_string(o.wg_threshold);
+    else if (k == "small_max") v = std::to_string(o.small_max);
     else if (k == "timeout_s") v = std::to_string(o.timeout_s);
     else return (int)fail(MCM_EINVAL, "unknown option '%s'", key);
     snprintf(buf, (size_t)len, "%s", v.c_str());
@@ -534,7 +554,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
         loop = 2;
         int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
         int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
-        record_stats(w.h_ctrl, init_card, card, ms, loop, flags);
+        record_stats(w.h_ctrl, init_card, card, ms, loop, flags, w.info.clock_khz);
         if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
         return card;
     }
@@ -552,17 +572,15 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     g.fq1 = w.fq + ncols;
     g.ends = w.ends;
     g.clevel = nullptr;
-    HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, flags, st));
-    HIPCHK(hipEventRecord(w.ev0, st));
+    HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, w.bar, flags, st));
     if ((rc = run_graph(w, o, g, flags, st, &loop))) return rc;
-    HIPCHK(hipEventRecord(w.ev1, st));
     HIPCHK(launch_finish(g, out_rmatch, w.ctrl, st));
     HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipEventElapsedTime(&ms, w.ev0, w.ev1));
     const int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
     const int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
-    record_stats(w.h_ctrl, init_card, card, ms, loop, flags);
+    record_stats(w.h_ctrl, init_card, card, ms, loop, flags, w.info.clock_khz);
     if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
     return card;
 }
@@ -590,7 +608,7 @@ static int64_t one_bfs_phase(Workspace &w, const Options &o, int32_t nc, int32_t
     g.clevel = clevel;
     uint32_t flags = F_NOAUG | (clevel ? F_LEVELS : 0u);
     if (o.mapping != 0) flags |= F_WAVE;
-    HIPCHK(launch_setup(g, cm, rm, w.ctrl, flags, st));
+    HIPCHK(launch_setup(g, cm, rm, w.ctrl, w.bar, flags, st));
     int loop = 0;
     Options oo = o;
     if ((rc = run_graph(w, oo, g, flags, st, &loop))) return rc;

@@ -8,8 +8,8 @@ namespace mcm {
 // own 128-byte line so that atomics on one do not contend with polls of
 // another.
 enum CtrlLine : int {
-    L_BAR_COUNT = 0,   // grid barrier arrivals
-    L_BAR_GEN,         // grid barrier generation
+    L_QUEUE = 0,       // graph queue head of the one-workgroup-per-graph kernel
+    L_BAR_GEN,         // grid barrier: epoch released by block 0
     L_FCOUNT0,         // frontier sizes, rotating over three levels
     L_FCOUNT1,
     L_FCOUNT2,
@@ -21,13 +21,18 @@ enum CtrlLine : int {
     L_PHASE,           // phases run (== stamp of the last phase)
     L_LEVELS,          // BFS levels expanded, all phases
     L_CARD,            // |M| (64-bit)
+    L_CURLEVEL,        // level reached by a run of single-workgroup levels
+    L_STOP,            // that run ended on a level that reached an unmatched row (APsB)
+    L_SMALL_LEVELS,    // levels expanded by single-workgroup runs (counter)
     L_STAT0,           // stats counters (64-bit each, own lines)
-    L_NLINES = L_STAT0 + 8
+    L_NLINES = L_STAT0 + 12
 };
-constexpr int kLineWords = 32;  // 128 B / 4 B
+constexpr int kLineWords = 32;        // 128 B / 4 B
+constexpr int kMaxGridBlocks = 2048;  // arrival flags of the grid barrier, one line each
 
 enum StatIdx : int {
-    S_EDGES = 0, S_EXPANDED, S_CLAIMED, S_FOUND, S_ALT, S_FIX, S_BATCH_LEVELS, S_SPARE
+    S_EDGES = 0, S_EXPANDED, S_CLAIMED, S_FOUND, S_ALT, S_FIX, S_ROOTS,
+    S_T_EXPAND, S_T_FLUSH, S_T_BARRIER, S_T_SMALL, S_T_AUGMENT  // wall-clock ticks seen by block 0 (stats=1)
 };
 
 enum Flags : uint32_t {
@@ -58,6 +63,7 @@ struct RunOpt {
     uint32_t flags;        // Flags
     uint32_t max_phases;   // watchdog: phases
     uint32_t max_levels;   // watchdog: levels per phase
+    uint32_t small_max;    // frontiers up to this size are expanded by one workgroup (0 = never)
     uint64_t timeout;      // wall-clock ticks a grid barrier may wait
 };
 
@@ -66,5 +72,12 @@ struct BatchDesc {
     int32_t nc, nr;
     int64_t colptr_off, rowind_off, col_off, row_off;
 };
+
+// Per-wavefront LDS staging of queue pushes.
+constexpr int kStageQ = 256;   // frontier entries per wavefront
+constexpr int kStageE = 128;   // unmatched-row ends per wavefront
+constexpr int kMaxWaves = 16;  // 1024-thread workgroups
+// dynamic LDS bytes for a workgroup of `waves` wavefronts
+inline constexpr int stage_lds_bytes(int waves) { return waves * (kStageQ * 16 + kStageE * 4) + 64 * 4; }
 
 }  // namespace mcm

@@ -2,10 +2,13 @@
 // expansion of GPUBFS / GPUBFS-WR (paper, Algorithms 2 and 4), Alternate
 // (Algorithm 3), FixMatching, and the phase/level loop of Algorithm 1
 // (APFB or APsB), in three launch forms:
-//   * k_persistent  -- the whole match in one cooperative launch; levels,
-//                      Alternate and Fix separated by a grid barrier;
+//   * k_persistent  -- the whole match in one cooperative launch.  Levels
+//                      with a large frontier are expanded by every block and
+//                      separated by a grid barrier; a run of levels whose
+//                      frontier stays small is expanded by block 0 alone,
+//                      with workgroup barriers only;
 //   * k_init_roots / k_level / k_alternate / k_fix -- one launch per step,
-//                      driven by a host loop;
+//                      driven by a host loop (the paper's arrangement);
 //   * k_match_wg    -- one workgroup matches one graph from start to end
 //                      (small graphs, and the batched entry point).
 //
@@ -19,7 +22,7 @@
 //            dependent gather.
 //   frontier entries int4 {col, root, beg, end}: the BFS-tree root travels
 //   with the entry (the paper's root[] array, Algorithm 4) and the column's
-//   adjacency range is fetched once when the column is claimed.
+//   adjacency range is fetched once, when the column is claimed.
 //   cdone[root] = phase stamp once the tree of `root` reached an unmatched
 //   row (the paper's bfs_array[root] = L0 - 2, Algorithm 4).
 //
@@ -28,7 +31,15 @@
 // once per phase and pred/root always describe the claimer.  Alternate's
 // flips race exactly as in the paper; the predecessor check (Algorithm 3)
 // stops a walk on a column another walk already flipped, and FixMatching
-// unmatches every row whose column does not point back.
+// unmatches every row whose column does not point back.  Work confined to
+// one workgroup (a single-workgroup run of levels, a graph of the batched
+// kernel) uses workgroup-scope atomics, which complete in the CU's L2
+// instead of travelling to the memory-side coherence point.
+//
+// Queue pushes are staged per wavefront in LDS (ballot + popcount
+// compaction) and reach the global queue in blocks: one atomic per staged
+// batch of up to kStageQ entries and one per workgroup at the end of a
+// level, instead of one per wavefront per 64 edges.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -41,12 +52,18 @@ namespace mcm {
 constexpr int kEInternal = -5;  // MCM_EINTERNAL
 constexpr int kEInval = -1;     // MCM_EINVAL
 constexpr int kEBadInit = -4;   // MCM_EBADINIT
+constexpr int kAgent = __HIP_MEMORY_SCOPE_AGENT;
+constexpr int kGroup = __HIP_MEMORY_SCOPE_WORKGROUP;
 
 DEV uint32_t *line(uint32_t *ctrl, int l) { return ctrl + l * kLineWords; }
 
-DEV uint32_t ld_agent(const uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-DEV int32_t ld_agent_i(const int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-DEV void st_agent_i(int32_t *p, int32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+template <int S> DEV uint32_t ld_u(const uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, S); }
+template <int S> DEV int32_t ld_i(const int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, S); }
+template <int S> DEV void st_i(int32_t *p, int32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, S); }
+template <int S> DEV bool cas_u64(uint64_t *p, uint64_t expect, uint64_t desired)
+{
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED, S);
+}
 
 DEV void set_status(uint32_t *ctrl, int code)
 {
@@ -54,7 +71,15 @@ DEV void set_status(uint32_t *ctrl, int code)
     atomicCAS(s, 0, code);
 }
 
-DEV int32_t status_of(uint32_t *ctrl) { return ld_agent_i(reinterpret_cast<int32_t *>(line(ctrl, L_STATUS))); }
+DEV int32_t status_of(uint32_t *ctrl) { return ld_i<kAgent>(reinterpret_cast<int32_t *>(line(ctrl, L_STATUS))); }
+
+// LDS written by some lanes of a wavefront and read by others
+DEV void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // inclusive prefix sum across the 64 lanes of a wavefront
 DEV int wave_incl_scan(int x)
@@ -75,44 +100,115 @@ DEV int wave_max(int x)
     return x;
 }
 
-// Append `item` for every lane with p set; one atomic per wavefront reserves
-// the slots, lanes write compacted (ballot + popcount prefix).
+DEV uint64_t wave_sum(uint64_t x)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+DEV uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+// ---------------------------------------------------------------------
+// Per-wavefront staging of queue pushes.
+struct Stage {
+    int4 *q;      // LDS [kStageQ] frontier entries of this wavefront
+    int32_t *e;   // LDS [kStageE] unmatched-row ends
+    int nq, ne;   // fill (wavefront-uniform)
+};
+
+DEV Stage make_stage(char *smem)
+{
+    const int waves = blockDim.x >> 6, w = threadIdx.x >> 6;
+    Stage s;
+    s.q = reinterpret_cast<int4 *>(smem) + w * kStageQ;
+    s.e = reinterpret_cast<int32_t *>(smem + waves * kStageQ * 16) + w * kStageE;
+    s.nq = s.ne = 0;
+    return s;
+}
+
+DEV uint32_t *stage_tmp(char *smem)
+{
+    const int waves = blockDim.x >> 6;
+    return reinterpret_cast<uint32_t *>(smem + waves * (kStageQ * 16 + kStageE * 4));
+}
+
 template <class T>
-DEV void wave_push(bool p, const T &item, T *q, uint32_t *cnt)
+DEV void stage_drain(T *buf, int &n, T *gq, uint32_t *gcnt)
+{
+    wave_lds_sync();
+    uint32_t base = 0;
+    if (__lane_id() == 0) base = atomicAdd(gcnt, (uint32_t)n);
+    base = __shfl(base, 0, 64);
+    for (int i = __lane_id(); i < n; i += 64) gq[base + i] = buf[i];
+    wave_lds_sync();
+    n = 0;
+}
+
+// Append `item` for every lane with p set (wavefront-uniform call).
+template <class T, int CAP>
+DEV void stage_push(bool p, const T &item, T *buf, int &n, T *gq, uint32_t *gcnt)
 {
     const uint64_t m = __ballot(p);
     if (m == 0) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
-    base = __shfl(base, leader, 64);
-    if (p) q[base + __popcll(m & ((1ull << lane) - 1ull))] = item;
+    if (n > CAP - 64) stage_drain(buf, n, gq, gcnt);
+    if (p) buf[n + __popcll(m & lanemask_lt())] = item;
+    n += __popcll(m);
 }
 
+// End of a level: every wavefront of the workgroup hands its staged entries
+// to the global queues with one atomic per queue for the whole workgroup.
+// All threads of the workgroup call it.
+DEV void block_flush(Stage &st, int4 *gq, uint32_t *gqcnt, int32_t *ge, uint32_t *gecnt, uint32_t *s_tmp)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = __lane_id();
+    wave_lds_sync();
+    if (lane == 0) { s_tmp[w] = (uint32_t)st.nq; s_tmp[16 + w] = (uint32_t)st.ne; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tq = 0, te = 0;
+        for (int i = 0; i < nw; ++i) {
+            const uint32_t a = s_tmp[i], b = s_tmp[16 + i];
+            s_tmp[i] = tq; tq += a;
+            s_tmp[16 + i] = te; te += b;
+        }
+        s_tmp[32] = tq ? atomicAdd(gqcnt, tq) : 0u;
+        s_tmp[33] = te ? atomicAdd(gecnt, te) : 0u;
+    }
+    __syncthreads();
+    const uint32_t bq = s_tmp[32] + s_tmp[w], be = s_tmp[33] + s_tmp[16 + w];
+    for (int i = lane; i < st.nq; i += 64) gq[bq + i] = st.q[i];
+    for (int i = lane; i < st.ne; i += 64) ge[be + i] = st.e[i];
+    st.nq = st.ne = 0;
+    __syncthreads();
+}
 
 // ---------------------------------------------------------------------
 // One scanned edge (col -> r) of the BFS (Algorithm 2 body; Algorithm 4
 // adds the root bookkeeping).  A matched, unvisited row is claimed and its
 // column becomes a next-frontier entry; an unmatched, unvisited row is
 // claimed as an augmenting-path end (rmatch = -2) and marks its root done.
+template <int S>
 DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, int level, uint32_t flags,
                     bool &newcol, int4 &ne, bool &newend)
 {
-    uint64_t w = g.rw[r];
+    // agent scope reads the memory-side copy, which other XCDs' claims
+    // update; a stale L2 copy would send every scanner of a popular row
+    // into a failing compare-and-swap
+    const uint64_t w = (S == kAgent) ? __hip_atomic_load(&g.rw[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : g.rw[r];
     if ((uint32_t)(w >> 32) == ph) return;           // reached earlier in this phase
     const int mate = (int)(uint32_t)w;
     if (mate >= 0) {
-        const uint64_t nw = ((uint64_t)ph << 32) | (uint32_t)mate;
-        if (atomicCAS((unsigned long long *)&g.rw[r], (unsigned long long)w, (unsigned long long)nw) == w) {
+        // adjacency range of the column behind r, fetched alongside the claim
+        const int b = g.colptr[mate], e = g.colptr[mate + 1];
+        if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | (uint32_t)mate)) {
             g.pred[r] = col;
-            ne = make_int4(mate, root, g.colptr[mate], g.colptr[mate + 1]);
+            ne = make_int4(mate, root, b, e);
             newcol = true;
             if (flags & F_LEVELS) g.clevel[mate] = level + 1;
         }
     } else if (mate == -1) {
-        const uint64_t nw = ((uint64_t)ph << 32) | 0xFFFFFFFEull;
-        if (atomicCAS((unsigned long long *)&g.rw[r], (unsigned long long)w, (unsigned long long)nw) == w) {
+        if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | 0xFFFFFFFEull)) {
             g.pred[r] = col;
             newend = true;
             if (flags & F_WR) g.cdone[root] = ph;
@@ -120,53 +216,75 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
     }
 }
 
-struct LevelCounters {
-    uint32_t *next;     // next frontier size
-    uint32_t *nends;    // ends found in this phase
-    uint32_t *found;    // set when this level reached an unmatched row
-    uint64_t *stats;    // [8] or null
+struct LevelIO {
+    int4 *nfq;          // next frontier
+    uint32_t *ncnt;     // its size
+    uint32_t *ecnt;     // ends found in this phase
+    uint32_t *found;    // set when this level reached an unmatched row (APsB)
 };
 
-DEV void flush_stats(uint64_t *stats, uint64_t edges, uint64_t expanded, uint64_t claimed, uint64_t found)
+DEV void add_stat(uint64_t *stats, int idx, uint64_t v)
 {
-    if (!stats) return;
-    // one atomic per counter per wavefront
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        edges += __shfl_xor(edges, o, 64);
-        expanded += __shfl_xor(expanded, o, 64);
-        claimed += __shfl_xor(claimed, o, 64);
-        found += __shfl_xor(found, o, 64);
-    }
-    if (__lane_id() == 0) {
-        if (edges) atomicAdd((unsigned long long *)&stats[S_EDGES * 16], (unsigned long long)edges);
-        if (expanded) atomicAdd((unsigned long long *)&stats[S_EXPANDED * 16], (unsigned long long)expanded);
-        if (claimed) atomicAdd((unsigned long long *)&stats[S_CLAIMED * 16], (unsigned long long)claimed);
-        if (found) atomicAdd((unsigned long long *)&stats[S_FOUND * 16], (unsigned long long)found);
-    }
+    v = wave_sum(v);
+    if (__lane_id() == 0 && v) atomicAdd((unsigned long long *)&stats[idx * 16], (unsigned long long)v);
 }
 
-// Expand frontier entries [0, n) of `fq`, wavefront `wave` of `nwaves`
-// taking batches of 64 entries.  WAVE: the edges of the 64 entries are
-// dealt out 64 at a time across the lanes (load balanced, coalesced rowind
-// reads); otherwise every lane walks its own column's edges.
-template <bool WAVE>
+// Per-lane counters (stats=1), accumulated over a whole run and added to
+// the control block once at the end.
+struct Acc {
+    uint64_t edges = 0, expanded = 0, claimed = 0, found = 0, alt = 0, fix = 0, roots = 0;
+    uint64_t t_expand = 0, t_flush = 0, t_barrier = 0, t_small = 0, t_augment = 0;
+    DEV void flush(uint64_t *stats)
+    {
+        add_stat(stats, S_EDGES, edges);
+        add_stat(stats, S_EXPANDED, expanded);
+        add_stat(stats, S_CLAIMED, claimed);
+        add_stat(stats, S_FOUND, found);
+        add_stat(stats, S_ALT, alt);
+        add_stat(stats, S_FIX, fix);
+        add_stat(stats, S_ROOTS, roots);
+        if (threadIdx.x == 0 && blockIdx.x == 0) {
+            stats[S_T_EXPAND * 16] += t_expand;
+            stats[S_T_FLUSH * 16] += t_flush;
+            stats[S_T_BARRIER * 16] += t_barrier;
+            stats[S_T_SMALL * 16] += t_small;
+            stats[S_T_AUGMENT * 16] += t_augment;
+        }
+    }
+};
+
+// Expand frontier entries [0, n) of `fq`; wavefront `wave` of `nwaves`
+// takes batches of 64 entries.  WAVE: the edges of the 64 entries are dealt
+// out 64 at a time across the lanes (load balanced, coalesced rowind
+// reads); otherwise every lane walks its own column's edges.  Every thread
+// of the workgroup calls it (it ends with a workgroup flush).
+// Entries per wavefront batch: spread a small frontier so that every busy
+// wavefront gets about one chunk of edges (latency), a large one in full
+// batches of 64 (throughput).
+DEV uint32_t batch_size(uint32_t n, uint32_t nwaves)
+{
+    const uint32_t b = (n + nwaves - 1) / nwaves;
+    return b < 1 ? 1u : (b > 64 ? 64u : b);
+}
+
+template <bool WAVE, int S>
 DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
-                      int level, uint32_t flags, int4 *nfq, const LevelCounters &lc)
+                      int level, uint32_t flags, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc)
 {
     const int lane = __lane_id();
-    uint64_t s_edges = 0, s_exp = 0, s_claim = 0, s_found = 0;
-    for (uint32_t base = wave * 64u; base < n; base += nwaves * 64u) {
+    const uint64_t t0 = (flags & F_STATS) ? wall_clock64() : 0;
+    bool any_end = false;
+    const uint32_t B = batch_size(n, nwaves);
+    for (uint32_t base = wave * B; base < n; base += nwaves * B) {
         const uint32_t i = base + lane;
         int4 e = make_int4(0, 0, 0, 0);
         int deg = 0;
-        if (i < n) {
+        if ((uint32_t)lane < B && i < n) {
             e = fq[i];
             deg = e.w - e.z;
             if ((flags & F_WR) && deg > 0 && g.cdone[e.y] == ph) deg = 0;  // root already has a path
         }
-        if (flags & F_STATS) { s_edges += deg; s_exp += (deg > 0); }
-        bool any_end = false;
+        if (flags & F_STATS) { acc.edges += deg; acc.expanded += (deg > 0); }
         if (WAVE) {
             const int incl = wave_incl_scan(deg);
             const int excl = incl - deg;
@@ -189,12 +307,12 @@ DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wa
                 int r = 0;
                 if (k < total) {
                     r = g.rowind[obeg + (k - oexcl)];
-                    visit_edge(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend);
+                    visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend);
                 }
-                wave_push(newcol, ne, nfq, lc.next);
-                wave_push(newend, r, g.ends, lc.nends);
+                stage_push<int4, kStageQ>(newcol, ne, st.q, st.nq, io.nfq, io.ncnt);
+                stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt);
                 any_end |= newend;
-                if (flags & F_STATS) { s_claim += newcol; s_found += newend; }
+                if (flags & F_STATS) { acc.claimed += newcol; acc.found += newend; }
             }
         } else {
             const int maxdeg = wave_max(deg);
@@ -204,24 +322,28 @@ DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wa
                 int r = 0;
                 if (t < deg) {
                     r = g.rowind[e.z + t];
-                    visit_edge(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend);
+                    visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend);
                 }
-                wave_push(newcol, ne, nfq, lc.next);
-                wave_push(newend, r, g.ends, lc.nends);
+                stage_push<int4, kStageQ>(newcol, ne, st.q, st.nq, io.nfq, io.ncnt);
+                stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt);
                 any_end |= newend;
-                if (flags & F_STATS) { s_claim += newcol; s_found += newend; }
+                if (flags & F_STATS) { acc.claimed += newcol; acc.found += newend; }
             }
         }
-        if ((flags & F_APSB) && __ballot(any_end) != 0 && lane == 0) atomicOr(lc.found, 1u);
     }
-    if (flags & F_STATS) flush_stats(lc.stats, s_edges, s_exp, s_claim, s_found);
+    if ((flags & F_APSB) && __ballot(any_end) != 0 && lane == 0) atomicOr(io.found, 1u);
+    const uint64_t t1 = (flags & F_STATS) ? wall_clock64() : 0;
+    block_flush(st, io.nfq, io.ncnt, g.ends, io.ecnt, s_tmp);
+    if (flags & F_STATS) { acc.t_expand += t1 - t0; acc.t_flush += wall_clock64() - t1; }
 }
 
 // InitBfsArray (paper, section 3, before Algorithm 2; root filled as in
 // Algorithm 4): every unmatched column with at least one edge becomes a
 // root and an entry of the first frontier.  Columns without edges can never
-// be matched and would expand nothing.
-DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, uint32_t flags, uint32_t *cnt)
+// be matched and would expand nothing.  Every thread of the workgroup calls
+// it.
+DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, uint32_t flags, uint32_t *cnt, Stage &st,
+                    uint32_t *s_tmp, Acc &acc)
 {
     const int lane = __lane_id();
     for (uint32_t base = wave * 64u; base < (uint32_t)g.nc; base += nwaves * 64u) {
@@ -236,42 +358,41 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, uint32_t 
             }
             if (flags & F_LEVELS) g.clevel[c] = un ? 0 : -1;
         }
-        wave_push(p, e, g.fq0, cnt);
+        if (flags & F_STATS) acc.roots += p;
+        stage_push<int4, kStageQ>(p, e, st.q, st.nq, g.fq0, cnt);
     }
+    block_flush(st, g.fq0, cnt, g.ends, nullptr, s_tmp);
 }
 
 // Alternate (Algorithm 3) from every reached unmatched row, one thread per
-// row.  Guard of a walk that arrives at a root (its column has no mate).
+// row.  A walk that reaches a root (its column has no mate) ends there.
+template <int S>
 DEV void alternate(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nthreads, uint32_t flags,
-                   uint32_t *ctrl, uint64_t *stats)
+                   uint32_t *ctrl, Acc &acc)
 {
     uint64_t steps = 0;
-    int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);  // low word of rw[r] is at rlo[2r]
+    int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);  // low word of rw[r] is rlo[2r]
     for (uint32_t i = tid; i < nends; i += nthreads) {
         int r = g.ends[i];
         uint32_t guard = 0;
         while (r != -1) {
-            const int c = ld_agent_i(&g.pred[r]);
-            const int r2 = ld_agent_i(&g.cmatch[c]);
-            if (r2 != -1 && ld_agent_i(&g.pred[r2]) == c) break;  // c already flipped by another walk
-            st_agent_i(&g.cmatch[c], r);
-            st_agent_i(&rlo[2 * (size_t)r], c);
+            const int c = ld_i<S>(&g.pred[r]);
+            const int r2 = ld_i<S>(&g.cmatch[c]);
+            if (r2 != -1 && ld_i<S>(&g.pred[r2]) == c) break;  // c already flipped by another walk
+            st_i<S>(&g.cmatch[c], r);
+            st_i<S>(&rlo[2 * (size_t)r], c);
             r = r2;
             ++steps;
             if (++guard > (uint32_t)g.nc + 1u) { set_status(ctrl, kEInternal); break; }
         }
     }
-    if ((flags & F_STATS) && stats) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) steps += __shfl_xor(steps, o, 64);
-        if (__lane_id() == 0 && steps) atomicAdd((unsigned long long *)&stats[S_ALT * 16], (unsigned long long)steps);
-    }
+    acc.alt += steps;
 }
 
 // FixMatching: a row whose column points elsewhere lost a race and is
 // unmatched; a row still marked -2 (its walk stopped before reaching it)
 // returns to -1.  cmatch is not touched.
-DEV void fix_matching(const DevGraph &g, uint32_t tid, uint32_t nthreads, uint32_t flags, uint64_t *stats)
+DEV void fix_matching(const DevGraph &g, uint32_t tid, uint32_t nthreads, uint32_t flags, Acc &acc)
 {
     uint64_t resets = 0;
     int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);
@@ -280,41 +401,50 @@ DEV void fix_matching(const DevGraph &g, uint32_t tid, uint32_t nthreads, uint32
         if (m == -1) continue;
         if (m < 0 || g.cmatch[m] != (int)r) { rlo[2 * (size_t)r] = -1; resets += (m >= 0); }
     }
-    if ((flags & F_STATS) && stats) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) resets += __shfl_xor(resets, o, 64);
-        if (__lane_id() == 0 && resets) atomicAdd((unsigned long long *)&stats[S_FIX * 16], (unsigned long long)resets);
-    }
+    acc.fix += resets;
 }
 
 // ---------------------------------------------------------------------
-// Grid barrier for the cooperative launch: arrival counter + generation,
-// agent-scope release before arriving and acquire after leaving, bounded
-// wait.  Returns false (all blocks, eventually) once any block set a
-// status, e.g. after a wait ran past the deadline.
-DEV bool grid_barrier(uint32_t *ctrl, uint32_t nblocks, uint64_t timeout, int *s_ok)
+// Grid barrier of the cooperative launch.  Every block but 0 publishes its
+// arrival in its own flag line (no shared counter, no contention); wave 0
+// of block 0 polls all flags, then releases the epoch.  Agent-scope release
+// before arriving, acquire after leaving; every wait is bounded.  Returns
+// false (in all blocks, eventually) once any block set a status.
+DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t timeout, int *s_ok)
 {
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        uint32_t *cnt = line(ctrl, L_BAR_COUNT);
-        uint32_t *gen = line(ctrl, L_BAR_GEN);
-        if (status_of(ctrl) != 0) {
-            ok = 0;
-        } else {
+    ++epoch;
+    uint32_t *gen = line(ctrl, L_BAR_GEN);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 64) {
+            int ok = status_of(ctrl) == 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const uint32_t g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev == nblocks - 1) {
-                __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(gen, g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-                    if (status_of(ctrl) != 0) { ok = 0; break; }
-                    if (wall_clock64() - t0 > timeout) { set_status(ctrl, kEInternal); ok = 0; break; }
-                    __builtin_amdgcn_s_sleep(1);
-                }
+            const uint64_t t0 = wall_clock64();
+            while (ok) {
+                bool mine = true;
+                for (uint32_t b = 1 + threadIdx.x; b < gridDim.x; b += 64)
+                    mine &= ld_u<kAgent>(bar + (size_t)b * kLineWords) == epoch;
+                if (__ballot(!mine) == 0) break;
+                if (status_of(ctrl) != 0) ok = 0;
+                else if (wall_clock64() - t0 > timeout) { if (threadIdx.x == 0) set_status(ctrl, kEInternal); ok = 0; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (threadIdx.x == 0) {
+                if (ok) __hip_atomic_store(gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                *s_ok = ok;
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        int ok = status_of(ctrl) == 0;
+        if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(bar + (size_t)blockIdx.x * kLineWords, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t t0 = wall_clock64();
+            while (ld_u<kAgent>(gen) != epoch) {
+                if (status_of(ctrl) != 0) { ok = 0; break; }
+                if (wall_clock64() - t0 > timeout) { set_status(ctrl, kEInternal); ok = 0; break; }
+                __builtin_amdgcn_s_sleep(1);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
@@ -325,91 +455,182 @@ DEV bool grid_barrier(uint32_t *ctrl, uint32_t nblocks, uint64_t timeout, int *s
 }
 
 // ---------------------------------------------------------------------
-// The phase loop of Algorithm 1, parameterised by how work is spread and
-// synchronised: Grid (cooperative launch, all blocks) or Block (one
-// workgroup owns the graph).
-struct GridSync {
-    uint32_t *ctrl;
-    uint64_t timeout;
-    int *s_ok;
-    DEV uint32_t wave() const { return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); }
-    DEV uint32_t nwaves() const { return gridDim.x * (blockDim.x >> 6); }
-    DEV uint32_t tid() const { return blockIdx.x * blockDim.x + threadIdx.x; }
-    DEV uint32_t nthreads() const { return gridDim.x * blockDim.x; }
-    DEV bool leader() const { return blockIdx.x == 0 && threadIdx.x == 0; }
-    DEV bool sync() { return grid_barrier(ctrl, gridDim.x, timeout, s_ok); }
-    DEV uint32_t load(uint32_t *p) const { return ld_agent(p); }
-};
+// A run of levels with small frontiers, expanded by the calling workgroup
+// alone (block 0 of the persistent kernel).  Starts at level L with n0
+// entries in the current queue, stops when the frontier is empty or larger
+// than small_max (or, APsB, after a level that reached an unmatched row).
+// Counters live in LDS (s_loc[0..2] frontier sizes, [3] found, [4] ends)
+// and are written back to the control block at the end, with the level
+// reached in L_CURLEVEL.  Returns the number of levels expanded.
+// Bound on one run, so that the blocks waiting at the grid barrier see
+// progress well within their wait limit.
+constexpr uint32_t kSmallRunLevels = 4096;
 
-struct BlockSync {
-    DEV uint32_t wave() const { return threadIdx.x >> 6; }
-    DEV uint32_t nwaves() const { return blockDim.x >> 6; }
-    DEV uint32_t tid() const { return threadIdx.x; }
-    DEV uint32_t nthreads() const { return blockDim.x; }
-    DEV bool leader() const { return threadIdx.x == 0; }
-    DEV bool sync() { __syncthreads(); return true; }
-    DEV uint32_t load(uint32_t *p) const { return *(volatile uint32_t *)p; }
-};
-
-// Counters of one run: either lines of the global control block (grid) or
-// a small LDS array (block).  cnt[0..2] frontier sizes, cnt[3..5] found
-// flags, cnt[6] ends, cnt[7] status (block only); `stride` words apart.
-struct Counters {
-    uint32_t *base;
-    int stride;
-    DEV uint32_t *fcount(int i) const { return base + (L_FCOUNT0 + i) * stride; }
-    DEV uint32_t *found(int i) const { return base + (L_FOUND0 + i) * stride; }
-    DEV uint32_t *nends() const { return base + L_NENDS * stride; }
-};
-
-// Runs phases until one finds no unmatched row (or only one phase with
-// F_NOAUG).  Returns false if a barrier failed (status set).  *phases_out
-// and *levels_out receive the phase and level counts (leader only).
-template <bool WAVE, class Sync>
-DEV bool run_phases(const DevGraph &g, Sync &s, const Counters &k, const RunOpt &o, uint32_t *ctrl, uint64_t *stats,
-                    uint32_t *phases_out, uint32_t *levels_out)
+template <bool WAVE>
+DEV uint32_t small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t ph, int L, uint32_t n0,
+                          Stage &st, uint32_t *s_tmp, uint32_t *s_loc, Acc &acc)
 {
-    uint32_t total_levels = 0;
-    uint32_t ph = 1;
+    const uint32_t flags = o.flags;
+    if (threadIdx.x == 0) {
+        s_loc[L % 3] = n0;
+        s_loc[(L + 1) % 3] = 0;
+        s_loc[(L + 2) % 3] = 0;
+        s_loc[3] = 0;
+        s_loc[4] = ld_u<kAgent>(line(ctrl, L_NENDS));
+    }
+    __syncthreads();
+    uint32_t levels = 0, stop = 0;
+    const uint32_t wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    for (;;) {
+        const uint32_t n = *(volatile uint32_t *)&s_loc[L % 3];
+        if (n == 0 || n > o.small_max || levels >= kSmallRunLevels) break;
+        if ((uint32_t)L > o.max_levels) { if (threadIdx.x == 0) set_status(ctrl, kEInternal); break; }
+        __syncthreads();
+        if (threadIdx.x == 0) { s_loc[(L + 2) % 3] = 0; s_loc[3] = 0; }
+        __syncthreads();
+        const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
+        LevelIO io{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], &s_loc[4], &s_loc[3]};
+        expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, flags, io, st, s_tmp, acc);
+        ++levels;
+        if ((flags & F_APSB) && *(volatile uint32_t *)&s_loc[3]) { stop = 1; break; }
+        ++L;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 3; ++i) {
+            *line(ctrl, L_FCOUNT0 + i) = (i == L % 3) ? s_loc[L % 3] : 0u;
+            *line(ctrl, L_FOUND0 + i) = 0;
+        }
+        *line(ctrl, L_NENDS) = s_loc[4];
+        *line(ctrl, L_CURLEVEL) = (uint32_t)L;
+        *line(ctrl, L_STOP) = stop;
+        *line(ctrl, L_SMALL_LEVELS) += levels;
+    }
+    return levels;
+}
+
+// The phase loop of Algorithm 1 over the whole grid (cooperative launch).
+template <bool WAVE>
+DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt &o, uint64_t *stats, Stage &st,
+                  uint32_t *s_tmp, uint32_t *s_loc, int *s_ok, uint32_t *ph_out, uint32_t *lv_out)
+{
+    const uint32_t flags = o.flags;
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nthreads = gridDim.x * blockDim.x;
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool timing = (flags & F_STATS) != 0;
+    Acc acc;
+    uint32_t epoch = 0, total_levels = 0, ph = 1;
+    auto fc = [&](int i) { return line(ctrl, L_FCOUNT0 + i); };
+    auto fd = [&](int i) { return line(ctrl, L_FOUND0 + i); };
+    // grid barrier, with the time block 0 spends in it counted (stats=1)
+    auto sync = [&]() -> bool {
+        const uint64_t t0 = timing ? wall_clock64() : 0;
+        const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok);
+        if (timing) acc.t_barrier += wall_clock64() - t0;
+        return ok;
+    };
     for (;; ++ph) {
-        if (ph > o.max_phases) { if (s.leader()) set_status(ctrl, kEInternal); return false; }
-        init_roots(g, s.wave(), s.nwaves(), o.flags, k.fcount(0));
-        if (!s.sync()) return false;
+        if (ph > o.max_phases) { if (leader) set_status(ctrl, kEInternal); return false; }
+        init_roots(g, wave, nwaves, flags, fc(0), st, s_tmp, acc);
+        if (!sync()) return false;
         int L = 0;
         for (;;) {
-            const uint32_t n = s.load(k.fcount(L % 3));
+            const uint32_t n = ld_u<kAgent>(fc(L % 3));
             if (n == 0) break;
-            if ((uint32_t)L > o.max_levels) { if (s.leader()) set_status(ctrl, kEInternal); return false; }
-            if (s.leader()) { *k.fcount((L + 2) % 3) = 0; *k.found((L + 2) % 3) = 0; }
+            if ((uint32_t)L > o.max_levels) { if (leader) set_status(ctrl, kEInternal); return false; }
+            if (n <= o.small_max) {
+                if (blockIdx.x == 0) {
+                    const uint64_t t0 = timing ? wall_clock64() : 0;
+                    total_levels += small_levels<WAVE>(g, ctrl, o, ph, L, n, st, s_tmp, s_loc, acc);
+                    if (timing) acc.t_small += wall_clock64() - t0;
+                }
+                if (!sync()) return false;
+                L = (int)ld_u<kAgent>(line(ctrl, L_CURLEVEL));
+                if ((flags & F_APSB) && ld_u<kAgent>(line(ctrl, L_STOP))) break;
+                continue;
+            }
+            if (leader) { *fc((L + 2) % 3) = 0; *fd((L + 2) % 3) = 0; }
             const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
-            int4 *nxt = (L & 1) ? g.fq0 : g.fq1;
-            LevelCounters lc{k.fcount((L + 1) % 3), k.nends(), k.found(L % 3), (o.flags & F_STATS) ? stats : nullptr};
-            expand_level<WAVE>(g, cur, n, s.wave(), s.nwaves(), ph, L, o.flags, nxt, lc);
+            LevelIO io{(L & 1) ? g.fq0 : g.fq1, fc((L + 1) % 3), line(ctrl, L_NENDS), fd(L % 3)};
+            expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, flags, io, st, s_tmp, acc);
             ++total_levels;
-            if (!s.sync()) return false;
-            if ((o.flags & F_APSB) && s.load(k.found(L % 3)) != 0) break;
+            if (!sync()) return false;
+            if ((flags & F_APSB) && ld_u<kAgent>(fd(L % 3)) != 0) break;
             ++L;
         }
-        const uint32_t ne = s.load(k.nends());
-        if (ne == 0 || (o.flags & F_NOAUG)) break;
-        alternate(g, ne, s.tid(), s.nthreads(), o.flags, ctrl, stats);
-        if (!s.sync()) return false;
-        fix_matching(g, s.tid(), s.nthreads(), o.flags, stats);
-        if (s.leader()) {
-            for (int i = 0; i < 3; ++i) { *k.fcount(i) = 0; *k.found(i) = 0; }
-            *k.nends() = 0;
+        const uint32_t ne = ld_u<kAgent>(line(ctrl, L_NENDS));
+        if (ne == 0 || (flags & F_NOAUG)) break;
+        const uint64_t ta = timing ? wall_clock64() : 0;
+        alternate<kAgent>(g, ne, tid, nthreads, flags, ctrl, acc);
+        if (!sync()) return false;
+        fix_matching(g, tid, nthreads, flags, acc);
+        if (leader) {
+            for (int i = 0; i < 3; ++i) { *fc(i) = 0; *fd(i) = 0; }
+            *line(ctrl, L_NENDS) = 0;
         }
-        if (!s.sync()) return false;
+        if (!sync()) return false;
+        if (timing) acc.t_augment += wall_clock64() - ta;
     }
-    if (s.leader()) { *phases_out = ph; *levels_out = total_levels; }
+    if (leader) { *ph_out = ph; *lv_out = total_levels; }
+    if (timing) acc.flush(stats);
+    return true;
+}
+
+// The phase loop of Algorithm 1 inside one workgroup (graph owned by it).
+template <bool WAVE>
+DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint64_t *stats, Stage &st, uint32_t *s_tmp,
+                   uint32_t *s_loc, uint32_t *ph_out, uint32_t *lv_out)
+{
+    const uint32_t flags = o.flags;
+    const uint32_t wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    Acc acc;
+    uint32_t total_levels = 0, ph = 1;
+    for (;; ++ph) {
+        if (ph > o.max_phases) { if (threadIdx.x == 0) set_status(ctrl, kEInternal); return false; }
+        __syncthreads();
+        if (threadIdx.x == 0) for (int i = 0; i < 5; ++i) s_loc[i] = 0;
+        __syncthreads();
+        init_roots(g, wave, nwaves, flags, &s_loc[0], st, s_tmp, acc);
+        int L = 0;
+        for (;;) {
+            const uint32_t n = *(volatile uint32_t *)&s_loc[L % 3];
+            if (n == 0) break;
+            if ((uint32_t)L > o.max_levels) { if (threadIdx.x == 0) set_status(ctrl, kEInternal); return false; }
+            __syncthreads();
+            if (threadIdx.x == 0) { s_loc[(L + 2) % 3] = 0; s_loc[3] = 0; }
+            __syncthreads();
+            const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
+            LevelIO io{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], &s_loc[4], &s_loc[3]};
+            expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, flags, io, st, s_tmp, acc);
+            ++total_levels;
+            if ((flags & F_APSB) && *(volatile uint32_t *)&s_loc[3]) break;
+            ++L;
+        }
+        const uint32_t ne = *(volatile uint32_t *)&s_loc[4];
+        if (ne == 0 || (flags & F_NOAUG)) break;
+        alternate<kGroup>(g, ne, threadIdx.x, blockDim.x, flags, ctrl, acc);
+        __syncthreads();
+        fix_matching(g, threadIdx.x, blockDim.x, flags, acc);
+    }
+    __syncthreads();
+    if (flags & F_STATS) {
+        acc.t_expand = acc.t_flush = 0;  // per-graph timings are not meaningful summed over blocks
+        acc.flush(stats);
+    }
+    *ph_out = ph;
+    *lv_out = total_levels;
     return true;
 }
 
 // ---------------------------------------------------------------------
 // Kernels
 
-// Copy the initial matching into the working state, reset stamps.
-__global__ void k_setup(DevGraph g, const int32_t *init_c, const int32_t *init_r, uint32_t *ctrl, uint32_t flags)
+// Copy the initial matching into the working state, reset stamps, control
+// block and barrier flags.
+__global__ void k_setup(DevGraph g, const int32_t *init_c, const int32_t *init_r, uint32_t *ctrl, uint32_t *bar,
+                        uint32_t flags)
 {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nt = gridDim.x * blockDim.x;
@@ -423,6 +644,8 @@ __global__ void k_setup(DevGraph g, const int32_t *init_c, const int32_t *init_r
         if (flags & F_LEVELS) g.pred[r] = -1;
     }
     for (uint32_t i = tid; i < (uint32_t)(L_NLINES * kLineWords); i += nt) ctrl[i] = 0;
+    if (bar)
+        for (uint32_t i = tid; i < (uint32_t)(kMaxGridBlocks * kLineWords); i += nt) bar[i] = 0;
 }
 
 // Optional input validation (option validate=1).
@@ -454,14 +677,17 @@ __global__ void k_validate(int32_t nc, int32_t nr, const int32_t *colptr, const 
 }
 
 template <bool WAVE>
-__global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl, RunOpt o)
+__global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl, uint32_t *bar, RunOpt o)
 {
+    extern __shared__ __align__(16) char smem[];
     __shared__ int s_ok;
-    GridSync s{ctrl, o.timeout, &s_ok};
-    Counters k{ctrl, kLineWords};
+    __shared__ uint32_t s_loc[8];
+    Stage st = make_stage(smem);
+    uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
     uint32_t ph = 0, lv = 0;
-    if (run_phases<WAVE>(g, s, k, o, ctrl, stats, &ph, &lv) && s.leader()) {
+    if (run_grid<WAVE>(g, ctrl, bar, o, stats, st, s_tmp, s_loc, &s_ok, &ph, &lv) && blockIdx.x == 0 &&
+        threadIdx.x == 0) {
         *line(ctrl, L_PHASE) = ph;
         *line(ctrl, L_LEVELS) = lv;
     }
@@ -470,38 +696,48 @@ __global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl,
 // Host-driven steps (one launch each).
 __global__ void k_init_roots(DevGraph g, uint32_t *ctrl, uint32_t flags)
 {
-    GridSync s{ctrl, 0, nullptr};
-    init_roots(g, s.wave(), s.nwaves(), flags, line(ctrl, L_FCOUNT0));
+    extern __shared__ __align__(16) char smem[];
+    Stage st = make_stage(smem);
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nwaves = gridDim.x * (blockDim.x >> 6);
+    Acc acc;
+    init_roots(g, wave, nwaves, flags, line(ctrl, L_FCOUNT0), st, stage_tmp(smem), acc);
+    if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0))); }
 }
 
 template <bool WAVE>
 __global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint32_t n, uint32_t ph, int L, uint32_t flags)
 {
-    GridSync s{ctrl, 0, nullptr};
-    Counters k{ctrl, kLineWords};
-    if (s.leader()) { *k.fcount((L + 2) % 3) = 0; *k.found((L + 2) % 3) = 0; }
+    extern __shared__ __align__(16) char smem[];
+    Stage st = make_stage(smem);
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nwaves = gridDim.x * (blockDim.x >> 6);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *line(ctrl, L_FCOUNT0 + (L + 2) % 3) = 0;
+        *line(ctrl, L_FOUND0 + (L + 2) % 3) = 0;
+    }
     const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
-    int4 *nxt = (L & 1) ? g.fq0 : g.fq1;
-    LevelCounters lc{k.fcount((L + 1) % 3), k.nends(), k.found(L % 3),
-                     (flags & F_STATS) ? reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)) : nullptr};
-    expand_level<WAVE>(g, cur, n, s.wave(), s.nwaves(), ph, L, flags, nxt, lc);
+    LevelIO io{(L & 1) ? g.fq0 : g.fq1, line(ctrl, L_FCOUNT0 + (L + 1) % 3), line(ctrl, L_NENDS),
+               line(ctrl, L_FOUND0 + L % 3)};
+    Acc acc;
+    expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, flags, io, st, stage_tmp(smem), acc);
+    if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0))); }
 }
 
 __global__ void k_alternate(DevGraph g, uint32_t *ctrl, uint32_t flags)
 {
-    GridSync s{ctrl, 0, nullptr};
     const uint32_t ne = *line(ctrl, L_NENDS);
-    alternate(g, ne, s.tid(), s.nthreads(), flags, ctrl, reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)));
+    Acc acc;
+    alternate<kAgent>(g, ne, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, flags, ctrl, acc);
+    if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)));
 }
 
 __global__ void k_fix(DevGraph g, uint32_t *ctrl, uint32_t flags)
 {
-    GridSync s{ctrl, 0, nullptr};
-    fix_matching(g, s.tid(), s.nthreads(), flags, reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)));
-    if (s.leader()) {
-        Counters k{ctrl, kLineWords};
-        for (int i = 0; i < 3; ++i) { *k.fcount(i) = 0; *k.found(i) = 0; }
-        *k.nends() = 0;
+    Acc acc;
+    fix_matching(g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, flags, acc);
+    if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int i = 0; i < 3; ++i) { *line(ctrl, L_FCOUNT0 + i) = 0; *line(ctrl, L_FOUND0 + i) = 0; }
+        *line(ctrl, L_NENDS) = 0;
     }
 }
 
@@ -513,8 +749,7 @@ __global__ void k_finish(DevGraph g, int32_t *out_r, uint32_t *ctrl)
     for (uint32_t r = tid; r < (uint32_t)g.nr; r += nt) out_r[r] = (int32_t)(uint32_t)g.rw[r];
     uint64_t m = 0;
     for (uint32_t c = tid; c < (uint32_t)g.nc; c += nt) m += (g.cmatch[c] >= 0);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) m += __shfl_xor(m, o, 64);
+    m = wave_sum(m);
     if (__lane_id() == 0 && m) atomicAdd((unsigned long long *)line(ctrl, L_CARD), (unsigned long long)m);
 }
 
@@ -536,8 +771,7 @@ __global__ void k_cover(DevGraph g, uint32_t ph, uint8_t *col_cov, uint8_t *row_
         row_cov[r] = v;
         k += v;
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) k += __shfl_xor(k, o, 64);
+    k = wave_sum(k);
     if (__lane_id() == 0 && k) atomicAdd((unsigned long long *)line(ctrl, L_CARD), (unsigned long long)k);
 }
 
@@ -548,6 +782,11 @@ __global__ void k_export_pred(DevGraph g, uint32_t ph, int32_t *row_pred)
     const uint32_t nt = gridDim.x * blockDim.x;
     for (uint32_t r = tid; r < (uint32_t)g.nr; r += nt)
         row_pred[r] = ((uint32_t)(g.rw[r] >> 32) == ph) ? g.pred[r] : -1;
+}
+
+__global__ void k_zero_ctrl(uint32_t *ctrl)
+{
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(L_NLINES * kLineWords); i += blockDim.x) ctrl[i] = 0;
 }
 
 // ---------------------------------------------------------------------
@@ -562,11 +801,14 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
                                                    uint32_t *cdone_all, int4 *fq_all, int32_t *ends_all,
                                                    int64_t *card, uint32_t *ctrl, RunOpt o)
 {
-    __shared__ uint32_t s_cnt[L_NLINES];
+    extern __shared__ __align__(16) char smem[];
+    __shared__ uint32_t s_loc[8];
     __shared__ int32_t s_next;
+    __shared__ uint32_t s_m;
+    Stage st = make_stage(smem);
+    uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
-    uint32_t *queue = line(ctrl, L_BAR_COUNT);  // graph queue head (no grid barrier in this kernel)
-    BlockSync s;
+    uint32_t *queue = line(ctrl, L_QUEUE);
     for (;;) {
         if (threadIdx.x == 0) s_next = (int32_t)atomicAdd(queue, 1u);
         __syncthreads();
@@ -588,31 +830,25 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
         g.fq1 = fq_all + 2 * d.col_off + d.nc;
         g.ends = ends_all + d.row_off;
         g.clevel = nullptr;
-        // set up this graph's state
         for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
             g.cmatch[c] = init_c ? init_c[d.col_off + c] : -1;
             g.cdone[c] = 0;
         }
         for (int r = threadIdx.x; r < g.nr; r += blockDim.x)
             g.rw[r] = (uint64_t)(uint32_t)(init_r ? init_r[d.row_off + r] : -1);
-        for (int i = threadIdx.x; i < L_NLINES; i += blockDim.x) s_cnt[i] = 0;
+        if (threadIdx.x == 0) s_m = 0;
         __syncthreads();
-        Counters k{s_cnt, 1};
         uint32_t ph = 0, lv = 0;
-        const bool ok = (g.nc > 0 && g.nr > 0) ? run_phases<WAVE>(g, s, k, o, ctrl, stats, &ph, &lv) : true;
+        const bool ok = (g.nc > 0 && g.nr > 0) ? run_block<WAVE>(g, ctrl, o, stats, st, s_tmp, s_loc, &ph, &lv) : true;
         __syncthreads();
-        // unpack and count
         uint32_t m = 0;
         for (int r = threadIdx.x; r < g.nr; r += blockDim.x) out_r[d.row_off + r] = (int32_t)(uint32_t)g.rw[r];
         for (int c = threadIdx.x; c < g.nc; c += blockDim.x) m += (g.cmatch[c] >= 0);
-        __syncthreads();
-        if (threadIdx.x == 0) s_cnt[0] = 0;
-        __syncthreads();
-        if (m) atomicAdd(&s_cnt[0], m);
+        if (m) atomicAdd(&s_m, m);
         __syncthreads();
         if (threadIdx.x == 0) {
-            card[gi] = ok ? (int64_t)s_cnt[0] : (int64_t)kEInternal;
-            atomicAdd((unsigned long long *)line(ctrl, L_CARD), (unsigned long long)s_cnt[0]);
+            card[gi] = ok ? (int64_t)s_m : (int64_t)kEInternal;
+            atomicAdd((unsigned long long *)line(ctrl, L_CARD), (unsigned long long)s_m);
             atomicMax(line(ctrl, L_PHASE), ph);
             atomicAdd(line(ctrl, L_LEVELS), lv);
         }
@@ -620,13 +856,21 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
     }
 }
 
-__global__ void k_zero_ctrl(uint32_t *ctrl)
-{
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(L_NLINES * kLineWords); i += blockDim.x) ctrl[i] = 0;
-}
-
 // ---------------------------------------------------------------------
 // Launch helpers called by the host driver (mcm_api.cpp).
+
+static int clamp_blocks(int64_t work, int per, int lo, int hi)
+{
+    int64_t b = (work + per - 1) / per;
+    if (b < lo) b = lo;
+    if (b > hi) b = hi;
+    return (int)b;
+}
+
+static hipError_t allow_lds(const void *fn, int bytes)
+{
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
 
 hipError_t launch_zero_ctrl(uint32_t *ctrl, hipStream_t st)
 {
@@ -634,14 +878,11 @@ hipError_t launch_zero_ctrl(uint32_t *ctrl, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_setup(const DevGraph &g, const int32_t *ic, const int32_t *ir, uint32_t *ctrl, uint32_t flags,
-                        hipStream_t st)
+hipError_t launch_setup(const DevGraph &g, const int32_t *ic, const int32_t *ir, uint32_t *ctrl, uint32_t *bar,
+                        uint32_t flags, hipStream_t st)
 {
     const int64_t n = g.nc > g.nr ? g.nc : g.nr;
-    int blocks = (int)((n + 255) / 256);
-    if (blocks < 1) blocks = 1;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_setup, dim3(blocks), dim3(256), 0, st, g, ic, ir, ctrl, flags);
+    hipLaunchKernelGGL(k_setup, dim3(clamp_blocks(n, 256, 256, 8192)), dim3(256), 0, st, g, ic, ir, ctrl, bar, flags);
     return hipGetLastError();
 }
 
@@ -652,91 +893,78 @@ hipError_t launch_validate(int32_t nc, int32_t nr, const int32_t *cp, const int3
     return hipGetLastError();
 }
 
-hipError_t persistent_occupancy(bool wave, int block, int *blocks_per_cu)
+static const void *persistent_fn(bool wave)
 {
-    if (wave)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void *>(&k_persistent<true>), block, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void *>(&k_persistent<false>), block, 0);
+    return wave ? reinterpret_cast<const void *>(&k_persistent<true>) : reinterpret_cast<const void *>(&k_persistent<false>);
 }
 
-hipError_t launch_persistent(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, bool wave, int blocks, int block,
-                             hipStream_t st)
+hipError_t persistent_occupancy(bool wave, int block, int *blocks_per_cu)
 {
+    const int lds = stage_lds_bytes(block / 64);
+    hipError_t e = allow_lds(persistent_fn(wave), lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, persistent_fn(wave), block, lds);
+}
+
+hipError_t launch_persistent(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt &o, bool wave, int blocks,
+                             int block, hipStream_t st)
+{
+    if (blocks > kMaxGridBlocks) return hipErrorInvalidValue;
     DevGraph gg = g;
-    uint32_t *cc = ctrl;
+    uint32_t *cc = ctrl, *bb = bar;
     RunOpt oo = o;
-    void *args[] = {&gg, &cc, &oo};
-    const void *fn = wave ? reinterpret_cast<const void *>(&k_persistent<true>)
-                          : reinterpret_cast<const void *>(&k_persistent<false>);
-    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(block), args, 0, st);
+    void *args[] = {&gg, &cc, &bb, &oo};
+    return hipLaunchCooperativeKernel(persistent_fn(wave), dim3(blocks), dim3(block), args,
+                                      (unsigned)stage_lds_bytes(block / 64), st);
 }
 
 hipError_t launch_init_roots(const DevGraph &g, uint32_t *ctrl, uint32_t flags, hipStream_t st)
 {
-    int blocks = (int)((g.nc + 255) / 256);
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_init_roots, dim3(blocks), dim3(256), 0, st, g, ctrl, flags);
+    hipLaunchKernelGGL(k_init_roots, dim3(clamp_blocks(g.nc, 256, 1, 4096)), dim3(256), stage_lds_bytes(4), st, g,
+                       ctrl, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_level(const DevGraph &g, uint32_t *ctrl, uint32_t n, uint32_t ph, int L, uint32_t flags, bool wave,
                         int max_blocks, hipStream_t st)
 {
-    int blocks = (int)((n + 255) / 256);
-    if (blocks < 1) blocks = 1;
-    if (blocks > max_blocks) blocks = max_blocks;
+    const int blocks = clamp_blocks(n, 4, 1, max_blocks);  // about one entry per wavefront when n is small
     if (wave)
-        hipLaunchKernelGGL(k_level<true>, dim3(blocks), dim3(256), 0, st, g, ctrl, n, ph, L, flags);
+        hipLaunchKernelGGL(k_level<true>, dim3(blocks), dim3(256), stage_lds_bytes(4), st, g, ctrl, n, ph, L, flags);
     else
-        hipLaunchKernelGGL(k_level<false>, dim3(blocks), dim3(256), 0, st, g, ctrl, n, ph, L, flags);
+        hipLaunchKernelGGL(k_level<false>, dim3(blocks), dim3(256), stage_lds_bytes(4), st, g, ctrl, n, ph, L, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_alternate(const DevGraph &g, uint32_t *ctrl, uint32_t nends, uint32_t flags, hipStream_t st)
 {
-    int blocks = (int)((nends + 255) / 256);
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_alternate, dim3(blocks), dim3(256), 0, st, g, ctrl, flags);
+    hipLaunchKernelGGL(k_alternate, dim3(clamp_blocks(nends, 256, 1, 4096)), dim3(256), 0, st, g, ctrl, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_fix(const DevGraph &g, uint32_t *ctrl, uint32_t flags, hipStream_t st)
 {
-    int blocks = (int)((g.nr + 255) / 256);
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fix, dim3(blocks), dim3(256), 0, st, g, ctrl, flags);
+    hipLaunchKernelGGL(k_fix, dim3(clamp_blocks(g.nr, 256, 1, 4096)), dim3(256), 0, st, g, ctrl, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_finish(const DevGraph &g, int32_t *out_r, uint32_t *ctrl, hipStream_t st)
 {
     const int64_t n = g.nc > g.nr ? g.nc : g.nr;
-    int blocks = (int)((n + 255) / 256);
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_finish, dim3(blocks), dim3(256), 0, st, g, out_r, ctrl);
+    hipLaunchKernelGGL(k_finish, dim3(clamp_blocks(n, 256, 1, 4096)), dim3(256), 0, st, g, out_r, ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_cover(const DevGraph &g, uint32_t ph, uint8_t *cc, uint8_t *rc, uint32_t *ctrl, hipStream_t st)
 {
     const int64_t n = g.nc > g.nr ? g.nc : g.nr;
-    int blocks = (int)((n + 255) / 256);
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_cover, dim3(blocks), dim3(256), 0, st, g, ph, cc, rc, ctrl);
+    hipLaunchKernelGGL(k_cover, dim3(clamp_blocks(n, 256, 1, 4096)), dim3(256), 0, st, g, ph, cc, rc, ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_export_pred(const DevGraph &g, uint32_t ph, int32_t *row_pred, hipStream_t st)
 {
-    int blocks = (int)((g.nr + 255) / 256);
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_export_pred, dim3(blocks), dim3(256), 0, st, g, ph, row_pred);
+    hipLaunchKernelGGL(k_export_pred, dim3(clamp_blocks(g.nr, 256, 1, 4096)), dim3(256), 0, st, g, ph, row_pred);
     return hipGetLastError();
 }
 
@@ -745,12 +973,16 @@ hipError_t launch_match_wg(const BatchDesc *descs, const int32_t *order, int32_t
                            uint64_t *rw, int32_t *pred, uint32_t *cdone, int4 *fq, int32_t *ends, int64_t *card,
                            uint32_t *ctrl, const RunOpt &o, bool wave, int blocks, int block, hipStream_t st)
 {
+    const int lds = stage_lds_bytes(block / 64);
+    const void *fn = wave ? reinterpret_cast<const void *>(&k_match_wg<true>) : reinterpret_cast<const void *>(&k_match_wg<false>);
+    hipError_t e = allow_lds(fn, lds);
+    if (e != hipSuccess) return e;
     if (wave)
-        hipLaunchKernelGGL(k_match_wg<true>, dim3(blocks), dim3(block), 0, st, descs, order, ngraphs, cp, ri, ic, ir,
+        hipLaunchKernelGGL(k_match_wg<true>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, cp, ri, ic, ir,
                            cm, out_r, rw, pred, cdone, fq, ends, card, ctrl, o);
     else
-        hipLaunchKernelGGL(k_match_wg<false>, dim3(blocks), dim3(block), 0, st, descs, order, ngraphs, cp, ri, ic, ir,
-                           cm, out_r, rw, pred, cdone, fq, ends, card, ctrl, o);
+        hipLaunchKernelGGL(k_match_wg<false>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, cp, ri, ic,
+                           ir, cm, out_r, rw, pred, cdone, fq, ends, card, ctrl, o);
     return hipGetLastError();
 }
 

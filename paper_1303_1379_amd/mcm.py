@@ -40,7 +40,9 @@ class mcm_graph(ctypes.Structure):
 class mcm_stats(ctypes.Structure):
     _fields_ = [("phases", ctypes.c_int64), ("levels", ctypes.c_int64), ("edges_scanned", ctypes.c_int64),
                 ("cols_expanded", ctypes.c_int64), ("cols_claimed", ctypes.c_int64), ("rows_found", ctypes.c_int64),
-                ("alt_steps", ctypes.c_int64), ("fix_resets", ctypes.c_int64), ("init_card", ctypes.c_int64),
+                ("alt_steps", ctypes.c_int64), ("fix_resets", ctypes.c_int64), ("roots", ctypes.c_int64),
+                ("t_expand_ms", ctypes.c_double), ("t_flush_ms", ctypes.c_double), ("t_barrier_ms", ctypes.c_double),
+                ("t_small_ms", ctypes.c_double), ("t_augment_ms", ctypes.c_double), ("init_card", ctypes.c_int64),
                 ("card", ctypes.c_int64), ("kernel_ms", ctypes.c_double), ("loop", ctypes.c_int32),
                 ("mapping", ctypes.c_int32)]
 
