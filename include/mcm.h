@@ -121,6 +121,54 @@ int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs,
                           int64_t *out_card, void *stream);
 
 /*
+ * Batch plans: the descriptors of a fixed set of graphs are uploaded once
+ * and the launch sequence of mcm_match_batched (control reset, the
+ * one-workgroup-per-graph kernel, result copies) is captured in a hipGraph
+ * that every mcm_batch_plan_run replays.  The arrays named at creation stay
+ * bound to the plan: between runs the caller may change their contents
+ * (new initial matchings, even new graphs of the same sizes) but not the
+ * pointers.  With option "autotune" = "1" creation times every candidate
+ * configuration (mapping thread/wave x workgroup 256/512/1024 threads x
+ * wavefront batch 1/8/32 entries) on the plan's own graphs and keeps the
+ * fastest; the choice is cached per device and size class, in the file
+ * named by option "tuning" if set, and reused by later plans and by
+ * mcm_match_batched (mapping "auto").
+ *
+ *   mcm_batch_plan_create  same arguments as mcm_match_batched (no stream,
+ *                          no card array); *plan receives the handle.
+ *                          Returns MCM_OK or a negative mcm_status.  The
+ *                          plan owns its workspace (device memory of about
+ *                          28 bytes per row and 36 per column).
+ *   mcm_batch_plan_run     replays the plan on `stream`, synchronises it,
+ *                          writes |M_g| into out_card (HOST [ngraphs], or
+ *                          NULL); returns sum |M_g| or a negative status.
+ *   mcm_batch_plan_info    JSON description of the chosen configuration.
+ *   mcm_batch_plan_destroy releases everything (NULL is accepted).
+ */
+typedef struct mcm_batch_plan mcm_batch_plan;
+
+int64_t mcm_batch_plan_create(int32_t ngraphs, const mcm_graph *graphs,
+                              const int32_t *colptr_all, const int32_t *rowind_all,
+                              const int32_t *init_cmatch_all, const int32_t *init_rmatch_all,
+                              int32_t *out_cmatch_all, int32_t *out_rmatch_all,
+                              mcm_batch_plan **plan);
+int64_t mcm_batch_plan_run(mcm_batch_plan *plan, int64_t *out_card, void *stream);
+int mcm_batch_plan_info(const mcm_batch_plan *plan, char *buf, int32_t len);
+int mcm_batch_plan_destroy(mcm_batch_plan *plan);
+
+/*
+ * mcm_cheap_init -- a cheap initial matching computed on the device (the
+ * paper starts every algorithm from a cheap greedy matching, section 4).
+ * Parallel greedy: each column takes the first row of its stored adjacency
+ * that it can claim while still unmatched; the result is a maximal
+ * matching, schedule dependent (it generally differs from the sequential
+ * mcm_cheap_init_host).  cmatch[ncols], rmatch[nrows]: DEVICE outputs.
+ * Returns |M0| or a negative mcm_status.
+ */
+int64_t mcm_cheap_init(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                       int32_t *cmatch, int32_t *rmatch, void *stream);
+
+/*
  * mcm_konig_cover -- minimum vertex cover certifying a maximum matching
  * (Konig's theorem; section 2 states the Berge criterion it rests on).
  * Runs one complete alternating BFS from every unmatched column (GPUBFS,
@@ -184,7 +232,11 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              level
  *   "validate"  "0" (default) | "1"            check CSC and init on device
  *   "stats"     "0" (default) | "1"            count scanned edges etc.
- *   "tuning"    path of an autotuner cache file (JSON) or ""
+ *   "tuning"    path of an autotuner cache file (JSON lines) or ""
+ *   "autotune"  "0" (default) | "1"            batch plans time candidates
+ *   "block", "blocks_per_cu", "wg_block", "wg_threshold", "small_max",
+ *   "batch_min", "split", "timeout_s"          launch-shape details (see
+ *                                              the host driver)
  * Return MCM_OK or MCM_EINVAL (unknown key or value).  mcm_get_option
  * writes the current value into buf (NUL-terminated, truncated to len).
  */

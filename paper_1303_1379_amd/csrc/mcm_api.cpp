@@ -6,45 +6,23 @@
 // reporting, options and counters.  All matching arithmetic runs in the
 // kernels of mcm_kernels.hip; the only host-side computation is the greedy
 // initial matching, offered as its own entry point.
-#include <hip/hip_runtime.h>
+#include "mcm_host.h"
 
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <mutex>
 #include <numeric>
-#include <string>
-#include <vector>
-
-#include "../../include/mcm.h"
-#include "mcm_internal.h"
-
-namespace mcm {
-hipError_t launch_setup(const DevGraph &, const int32_t *, const int32_t *, uint32_t *, uint32_t *, uint32_t, hipStream_t);
-hipError_t launch_validate(int32_t, int32_t, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
-                           uint32_t *, hipStream_t);
-hipError_t persistent_occupancy(bool, int, int *);
-hipError_t launch_persistent(const DevGraph &, uint32_t *, uint32_t *, const RunOpt &, bool, int, int, hipStream_t);
-hipError_t launch_init_roots(const DevGraph &, uint32_t *, uint32_t, hipStream_t);
-hipError_t launch_level(const DevGraph &, uint32_t *, uint32_t, uint32_t, int, uint32_t, bool, int, hipStream_t);
-hipError_t launch_alternate(const DevGraph &, uint32_t *, uint32_t, uint32_t, hipStream_t);
-hipError_t launch_fix(const DevGraph &, uint32_t *, uint32_t, hipStream_t);
-hipError_t launch_finish(const DevGraph &, int32_t *, uint32_t *, hipStream_t);
-hipError_t launch_cover(const DevGraph &, uint32_t, uint8_t *, uint8_t *, uint32_t *, hipStream_t);
-hipError_t launch_export_pred(const DevGraph &, uint32_t, int32_t *, hipStream_t);
-hipError_t launch_match_wg(const BatchDesc *, const int32_t *, int32_t, const int32_t *, const int32_t *,
-                           const int32_t *, const int32_t *, int32_t *, int32_t *, uint64_t *, int32_t *, uint32_t *,
-                           int4 *, int32_t *, int64_t *, uint32_t *, const RunOpt &, bool, int, int, hipStream_t);
-hipError_t launch_zero_ctrl(uint32_t *, hipStream_t);
-}  // namespace mcm
 
 using namespace mcm;
 
-namespace {
+namespace mcm {
+namespace host {
 
 // ------------------------------------------------------------------ errors
 thread_local std::string t_err;
+
+const std::string &last_error() { return t_err; }
 
 int64_t fail(int64_t code, const char *fmt, ...)
 {
@@ -57,29 +35,8 @@ int64_t fail(int64_t code, const char *fmt, ...)
     return code;
 }
 
-#define HIPCHK(expr)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail(MCM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
-    } while (0)
 
 // ------------------------------------------------------------------ options
-struct Options {
-    bool apsb = false;        // driver
-    bool wr = true;           // bfs
-    int mapping = 2;          // 0 thread, 1 wave, 2 auto
-    int loop = 2;             // 0 device, 1 host, 2 auto
-    bool validate = false;
-    bool stats = false;
-    std::string tuning;
-    int block = 1024;         // persistent block size
-    int blocks_per_cu = 1;    // 0 = occupancy limit
-    int wg_block = 512;       // one-workgroup matcher block size
-    int64_t wg_threshold = 16384;  // nc + nr at or below which one workgroup matches alone
-    int64_t small_max = 256;  // frontiers up to this size are expanded by one workgroup
-    double timeout_s = 20.0;  // device barrier wait limit
-};
 Options g_opt;
 std::mutex g_opt_mu;
 
@@ -89,38 +46,12 @@ Options opts()
     return g_opt;
 }
 
-// ------------------------------------------------------------------ device info + workspace
-struct DevInfo {
-    int ncu = 0;
-    double clock_khz = 100000.0;
-};
-
-struct Workspace {
-    int device = -1;
-    size_t cap_nc = 0, cap_nr = 0;
-    uint64_t *rw = nullptr;
-    int32_t *pred = nullptr;
-    uint32_t *cdone = nullptr;
-    int4 *fq = nullptr;
-    int32_t *ends = nullptr;
-    int32_t *cwork = nullptr;
-    uint32_t *ctrl = nullptr;
-    uint32_t *bar = nullptr;     // grid barrier arrival flags
-    BatchDesc *desc = nullptr;
-    size_t cap_desc = 0;
-    int32_t *order = nullptr;
-    int64_t *card = nullptr;
-    uint32_t *h_ctrl = nullptr;  // pinned
-    BatchDesc *h_desc = nullptr; // pinned
-    int32_t *h_order = nullptr;  // pinned
-    int64_t *h_card = nullptr;   // pinned
-    size_t cap_hdesc = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    DevInfo info;
-};
-
+// ------------------------------------------------------------------ workspace
 std::mutex g_ws_mu;
 Workspace g_ws[64];
+
+Workspace &workspace(int dev) { return g_ws[dev]; }
+std::mutex &workspace_mutex() { return g_ws_mu; }
 mcm_stats g_stats;
 std::mutex g_stats_mu;
 
@@ -136,6 +67,7 @@ int64_t ensure_base(Workspace &w, int dev)
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, dev));
     w.info.ncu = prop.multiProcessorCount;
+    w.info.arch = prop.gcnArchName;
     int rate = 0;
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate > 0)
         w.info.clock_khz = rate;
@@ -147,19 +79,30 @@ int64_t ensure_base(Workspace &w, int dev)
     return 0;
 }
 
-int64_t ensure_graph(Workspace &w, size_t nc, size_t nr)
+// Grow-only workspace: per-column and per-row state for nc x nr, and two
+// frontier queues of at least qcap entries each (fq and fq + cap_q).
+int64_t ensure_graph(Workspace &w, size_t nc, size_t nr, size_t qcap)
 {
     if (nc > w.cap_nc) {
-        free_dev(w.cdone); free_dev(w.fq); free_dev(w.cwork);
-        w.cdone = nullptr; w.fq = nullptr; w.cwork = nullptr;
+        free_dev(w.cdone); free_dev(w.cwork);
+        w.cdone = nullptr; w.cwork = nullptr;
         size_t cap = std::max(nc, w.cap_nc + w.cap_nc / 2);
         if (hipMalloc(&w.cdone, sizeof(uint32_t) * cap) != hipSuccess ||
-            hipMalloc(&w.fq, sizeof(int4) * 2 * cap) != hipSuccess ||
             hipMalloc(&w.cwork, sizeof(int32_t) * cap) != hipSuccess) {
             w.cap_nc = 0;
             return fail(MCM_ENOMEM, "workspace allocation for %zu columns failed", nc);
         }
         w.cap_nc = cap;
+    }
+    if (qcap > w.cap_q) {
+        free_dev(w.fq);
+        w.fq = nullptr;
+        size_t cap = std::max(qcap, w.cap_q + w.cap_q / 2);
+        if (hipMalloc(&w.fq, sizeof(int4) * 2 * cap) != hipSuccess) {
+            w.cap_q = 0;
+            return fail(MCM_ENOMEM, "frontier queues of %zu entries failed", qcap);
+        }
+        w.cap_q = cap;
     }
     if (nr > w.cap_nr) {
         free_dev(w.rw); free_dev(w.pred); free_dev(w.ends);
@@ -199,6 +142,20 @@ int64_t ensure_desc(Workspace &w, size_t n)
 }
 
 uint32_t *ctrl_line(uint32_t *ctrl, int l) { return ctrl + l * kLineWords; }
+
+// Frontier entries per level: one per column, plus one per `split` edges
+// of a split column.  Reads nnz = colptr[nc] from the device.
+int64_t queue_capacity(int32_t nc, const int32_t *colptr, uint32_t split, hipStream_t st, size_t *qcap)
+{
+    *qcap = (size_t)nc + 1;
+    if (split == 0) return 0;
+    int32_t nnz = 0;
+    HIPCHK(hipMemcpyAsync(&nnz, colptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (nnz < 0) return fail(MCM_EINVAL, "colptr[ncols] = %d < 0", nnz);
+    *qcap += (size_t)nnz / split + 1;
+    return 0;
+}
 uint64_t ctrl_stat(uint32_t *ctrl, int s) { return reinterpret_cast<uint64_t *>(ctrl_line(ctrl, L_STAT0))[s * 16]; }
 
 RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info)
@@ -208,6 +165,8 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     r.max_phases = (uint32_t)std::min<int64_t>(nc + 2, 0x7fffffff);
     r.max_levels = (uint32_t)std::min<int64_t>(nc + 2, 0x7fffffff);
     r.small_max = (uint32_t)o.small_max;
+    r.batch_min = (uint32_t)o.batch_min;
+    r.split = (uint32_t)o.split;
     r.timeout = (uint64_t)(o.timeout_s * info.clock_khz * 1000.0);
     return r;
 }
@@ -248,13 +207,13 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
     HIPCHK(hipEventRecord(w.ev0, st));
     for (uint32_t ph = 1;; ++ph) {
         if (ph > ro.max_phases) return fail(MCM_EINTERNAL, "phase bound exceeded");
-        HIPCHK(launch_init_roots(g, w.ctrl, flags, st));
+        HIPCHK(launch_init_roots(g, w.ctrl, ro, st));
         if ((rc = readback())) return rc;
         uint32_t n = *ctrl_line(hc, L_FCOUNT0);
         int L = 0;
         while (n > 0) {
             if ((uint32_t)L > ro.max_levels) return fail(MCM_EINTERNAL, "level bound exceeded");
-            HIPCHK(launch_level(g, w.ctrl, n, ph, L, flags, wave, w.info.ncu * 8, st));
+            HIPCHK(launch_level(g, w.ctrl, n, ph, L, ro, wave, w.info.ncu * 8, st));
             ++levels;
             if ((rc = readback())) return rc;
             if ((flags & F_APSB) && *ctrl_line(hc, L_FOUND0 + (L % 3))) break;
@@ -296,7 +255,7 @@ int current_device(int *dev)
 }
 
 void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int loop, uint32_t flags,
-                  double clock_khz = 100000.0)
+                  double clock_khz)
 {
     std::lock_guard<std::mutex> lk(g_stats_mu);
     mcm_stats s{};
@@ -349,20 +308,38 @@ int64_t run_single_wg(Workspace &w, const Options &o, int32_t nc, int32_t nr, co
 {
     int64_t rc;
     if ((rc = ensure_desc(w, 1))) return rc;
-    w.h_desc[0] = BatchDesc{nc, nr, 0, 0, 0, 0};
+    BatchDesc d;
+    d.nc = nc;
+    d.nr = nr;
+    d.colptr = colptr;
+    d.rowind = rowind;
+    d.init_c = ic;
+    d.init_r = ir;
+    d.out_c = oc;
+    d.out_r = orr;
+    d.rw = w.rw;
+    d.pred = w.pred;
+    d.cdone = w.cdone;
+    d.fq = w.fq;
+    d.ends = w.ends;
+    w.h_desc[0] = d;
+    HIPCHK(prepare_match_wg(o.wg_block));
     HIPCHK(hipMemcpyAsync(w.desc, w.h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
     HIPCHK(launch_zero_ctrl(w.ctrl, st));
     RunOpt ro = run_opt(o, flags, nc, w.info);
+    ro.split = 0;  // the graph's queue slices hold exactly nc entries
     HIPCHK(hipEventRecord(w.ev0, st));
-    HIPCHK(launch_match_wg(w.desc, nullptr, 1, colptr, rowind, ic, ir, oc, orr, w.rw, w.pred, w.cdone, w.fq, w.ends,
-                           w.card, w.ctrl, ro, (flags & F_WAVE) != 0, 1, o.wg_block, st));
+    HIPCHK(launch_match_wg(w.desc, nullptr, 1, w.card, w.ctrl, ro, (flags & F_WAVE) != 0, 1, o.wg_block, st));
     HIPCHK(hipEventRecord(w.ev1, st));
     HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return 0;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace mcm
+
+using namespace mcm::host;
 
 // =================================================================== C ABI
 extern "C" {
@@ -423,6 +400,9 @@ int mcm_set_option(const char *key, const char *value)
         else return (int)fail(MCM_EINVAL, "stats must be 0 or 1");
     } else if (k == "tuning") {
         g_opt.tuning = v;
+    } else if (k == "autotune") {
+        if (v == "0" || v == "1") g_opt.autotune = v == "1";
+        else return (int)fail(MCM_EINVAL, "autotune must be 0 or 1");
     } else if (k == "block") {
         if (!as_int(64, 1024, &x) || x % 64) return (int)fail(MCM_EINVAL, "block must be a multiple of 64 in [64, 1024]");
         g_opt.block = (int)x;
@@ -435,6 +415,13 @@ int mcm_set_option(const char *key, const char *value)
     } else if (k == "wg_threshold") {
         if (!as_int(0, (int64_t)1 << 40, &x)) return (int)fail(MCM_EINVAL, "wg_threshold must be >= 0");
         g_opt.wg_threshold = x;
+    } else if (k == "batch_min") {
+        if (!as_int(1, 64, &x)) return (int)fail(MCM_EINVAL, "batch_min must be in [1, 64]");
+        g_opt.batch_min = (int)x;
+    } else if (k == "split") {
+        if (!as_int(0, (int64_t)1 << 30, &x) || (x != 0 && x < 64))
+            return (int)fail(MCM_EINVAL, "split must be 0 or in [64, 2^30]");
+        g_opt.split = (int)x;
     } else if (k == "small_max") {
         if (!as_int(0, (int64_t)1 << 30, &x)) return (int)fail(MCM_EINVAL, "small_max must be in [0, 2^30]");
         g_opt.small_max = x;
@@ -463,11 +450,14 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "validate") v = o.validate ? "1" : "0";
     else if (k == "stats") v = o.stats ? "1" : "0";
     else if (k == "tuning") v = o.tuning;
+    else if (k == "autotune") v = o.autotune ? "1" : "0";
     else if (k == "block") v = std::to_string(o.block);
     else if (k == "blocks_per_cu") v = std::to_string(o.blocks_per_cu);
     else if (k == "wg_block") v = std::to_string(o.wg_block);
     else if (k == "wg_threshold") v = std::to_string(o.wg_threshold);
     else if (k == "small_max") v = std::to_string(o.small_max);
+    else if (k == "batch_min") v = std::to_string(o.batch_min);
+    else if (k == "split") v = std::to_string(o.split);
     else if (k == "timeout_s") v = std::to_string(o.timeout_s);
     else return (int)fail(MCM_EINVAL, "unknown option '%s'", key);
     snprintf(buf, (size_t)len, "%s", v.c_str());
@@ -530,7 +520,10 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace &w = g_ws[dev];
     if ((rc = ensure_base(w, dev))) return rc;
-    if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows))) return rc;
+    const bool single_wg = (int64_t)ncols + nrows <= o.wg_threshold;
+    size_t qcap = 0;
+    if ((rc = queue_capacity(ncols, colptr, single_wg ? 0u : (uint32_t)o.split, st, &qcap))) return rc;
+    if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows, std::max(qcap, (size_t)ncols)))) return rc;
 
     if (o.validate) {
         HIPCHK(launch_zero_ctrl(w.ctrl, st));
@@ -546,7 +539,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     int loop = 0;
     float ms = 0.f;
     int64_t init_card = -1;
-    if ((int64_t)ncols + nrows <= o.wg_threshold) {
+    if (single_wg) {
         if ((rc = run_single_wg(w, o, ncols, nrows, colptr, rowind, init_cmatch, init_rmatch, out_cmatch, out_rmatch,
                                 flags, st)))
             return rc;
@@ -569,7 +562,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     g.pred = w.pred;
     g.cdone = w.cdone;
     g.fq0 = w.fq;
-    g.fq1 = w.fq + ncols;
+    g.fq1 = w.fq + w.cap_q;
     g.ends = w.ends;
     g.clevel = nullptr;
     HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, w.bar, flags, st));
@@ -592,7 +585,9 @@ static int64_t one_bfs_phase(Workspace &w, const Options &o, int32_t nc, int32_t
                              hipStream_t st, DevGraph *gout)
 {
     int64_t rc;
-    if ((rc = ensure_graph(w, (size_t)nc, (size_t)nr))) return rc;
+    size_t qcap = 0;
+    if ((rc = queue_capacity(nc, colptr, (uint32_t)o.split, st, &qcap))) return rc;
+    if ((rc = ensure_graph(w, (size_t)nc, (size_t)nr, qcap))) return rc;
     DevGraph g;
     g.colptr = colptr;
     g.rowind = rowind;
@@ -603,7 +598,7 @@ static int64_t one_bfs_phase(Workspace &w, const Options &o, int32_t nc, int32_t
     g.pred = w.pred;
     g.cdone = w.cdone;
     g.fq0 = w.fq;
-    g.fq1 = w.fq + nc;
+    g.fq1 = w.fq + w.cap_q;
     g.ends = w.ends;
     g.clevel = clevel;
     uint32_t flags = F_NOAUG | (clevel ? F_LEVELS : 0u);
@@ -676,75 +671,6 @@ int64_t mcm_bfs_levels(int32_t ncols, int32_t nrows, const int32_t *colptr, cons
     HIPCHK(launch_export_pred(g, 1, row_pred, st));
     HIPCHK(hipStreamSynchronize(st));
     return (int64_t)*ctrl_line(w.h_ctrl, L_NENDS);
-}
-
-int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs, const int32_t *colptr_all,
-                          const int32_t *rowind_all, const int32_t *init_cmatch_all, const int32_t *init_rmatch_all,
-                          int32_t *out_cmatch_all, int32_t *out_rmatch_all, int64_t *out_card, void *stream)
-{
-    if (ngraphs < 0) return fail(MCM_EINVAL, "ngraphs < 0");
-    if (ngraphs == 0) return 0;
-    if (!graphs) return fail(MCM_EINVAL, "graphs is NULL");
-    if ((init_cmatch_all == nullptr) != (init_rmatch_all == nullptr))
-        return fail(MCM_EINVAL, "init arrays must both be NULL or both be given");
-    if (!colptr_all || !out_cmatch_all || !out_rmatch_all) return fail(MCM_EINVAL, "NULL packed array");
-    int64_t col_ext = 0, row_ext = 0;
-    for (int32_t i = 0; i < ngraphs; ++i) {
-        const mcm_graph &d = graphs[i];
-        if (d.ncols < 0 || d.nrows < 0 || d.colptr_off < 0 || d.rowind_off < 0 || d.col_off < 0 || d.row_off < 0)
-            return fail(MCM_EINVAL, "graph %d: negative size or offset", i);
-        if (d.ncols > 0 && d.nrows > 0 && !rowind_all) return fail(MCM_EINVAL, "rowind_all is NULL");
-        col_ext = std::max(col_ext, d.col_off + d.ncols);
-        row_ext = std::max(row_ext, d.row_off + d.nrows);
-    }
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    int dev = 0;
-    if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
-    const Options o = opts();
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace &w = g_ws[dev];
-    int64_t rc;
-    if ((rc = ensure_base(w, dev))) return rc;
-    if ((rc = ensure_graph(w, (size_t)std::max<int64_t>(col_ext, 1), (size_t)std::max<int64_t>(row_ext, 1)))) return rc;
-    if ((rc = ensure_desc(w, (size_t)ngraphs))) return rc;
-    // the frontier slices are 2*col_off .. 2*col_off + 2*nc: workspace fq holds 2*cap_nc entries
-    std::vector<int32_t> order(ngraphs);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return (int64_t)graphs[a].ncols + graphs[a].nrows > (int64_t)graphs[b].ncols + graphs[b].nrows;
-    });
-    for (int32_t i = 0; i < ngraphs; ++i) {
-        const mcm_graph &d = graphs[i];
-        w.h_desc[i] = BatchDesc{d.ncols, d.nrows, d.colptr_off, d.rowind_off, d.col_off, d.row_off};
-        w.h_order[i] = order[i];
-    }
-    HIPCHK(hipMemcpyAsync(w.desc, w.h_desc, sizeof(BatchDesc) * ngraphs, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(w.order, w.h_order, sizeof(int32_t) * ngraphs, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_zero_ctrl(w.ctrl, st));
-    uint32_t flags = base_flags(o, 0, 0);
-    RunOpt ro = run_opt(o, flags, std::max<int64_t>(col_ext, 1), w.info);
-    int blocks = std::min<int64_t>(ngraphs, (int64_t)w.info.ncu * 4);
-    HIPCHK(hipEventRecord(w.ev0, st));
-    HIPCHK(launch_match_wg(w.desc, w.order, ngraphs, colptr_all, rowind_all, init_cmatch_all, init_rmatch_all,
-                           out_cmatch_all, out_rmatch_all, w.rw, w.pred, w.cdone, w.fq, w.ends, w.card, w.ctrl, ro,
-                           (flags & F_WAVE) != 0, blocks, o.wg_block, st));
-    HIPCHK(hipEventRecord(w.ev1, st));
-    HIPCHK(hipMemcpyAsync(w.h_card, w.card, sizeof(int64_t) * ngraphs, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, w.ev0, w.ev1));
-    int64_t total = 0;
-    bool bad = false;
-    for (int32_t i = 0; i < ngraphs; ++i) {
-        if (w.h_card[i] < 0) bad = true;
-        else total += w.h_card[i];
-        if (out_card) out_card[i] = w.h_card[i];
-    }
-    record_stats(w.h_ctrl, -1, total, ms, 2, flags);
-    const int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
-    if (bad || s != 0) return fail(MCM_EINTERNAL, "device watchdog fired in a batched graph (status %d)", s);
-    return total;
 }
 
 }  // extern "C"

@@ -1,0 +1,118 @@
+// Host-side internals shared by the C ABI sources (mcm_api.cpp,
+// mcm_batch.cpp, mcm_server.cpp): launch helpers of mcm_kernels.hip,
+// options, the per-device workspace, error reporting.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+
+#include "../../include/mcm.h"
+#include "mcm_internal.h"
+
+namespace mcm {
+
+// ---- launch helpers (mcm_kernels.hip)
+hipError_t launch_zero_ctrl(uint32_t *ctrl, hipStream_t st);
+hipError_t launch_setup(const DevGraph &, const int32_t *, const int32_t *, uint32_t *, uint32_t *, uint32_t,
+                        hipStream_t);
+hipError_t launch_validate(int32_t, int32_t, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
+                           uint32_t *, hipStream_t);
+hipError_t persistent_occupancy(bool, int, int *);
+hipError_t launch_persistent(const DevGraph &, uint32_t *, uint32_t *, const RunOpt &, bool, int, int, hipStream_t);
+hipError_t launch_init_roots(const DevGraph &, uint32_t *, const RunOpt &, hipStream_t);
+hipError_t launch_level(const DevGraph &, uint32_t *, uint32_t, uint32_t, int, const RunOpt &, bool, int, hipStream_t);
+hipError_t launch_alternate(const DevGraph &, uint32_t *, uint32_t, uint32_t, hipStream_t);
+hipError_t launch_fix(const DevGraph &, uint32_t *, uint32_t, hipStream_t);
+hipError_t launch_finish(const DevGraph &, int32_t *, uint32_t *, hipStream_t);
+hipError_t launch_cover(const DevGraph &, uint32_t, uint8_t *, uint8_t *, uint32_t *, hipStream_t);
+hipError_t launch_export_pred(const DevGraph &, uint32_t, int32_t *, hipStream_t);
+hipError_t launch_match_wg(const BatchDesc *descs, const int32_t *order, int32_t ngraphs, int64_t *card,
+                           uint32_t *ctrl, const RunOpt &o, bool wave, int blocks, int block, hipStream_t st);
+hipError_t prepare_match_wg(int block);
+hipError_t match_wg_occupancy(bool wave, int block, int *per_cu);
+hipError_t launch_cheap_init(const BatchDesc *descs, int32_t ngraphs, hipStream_t st);
+
+namespace host {
+
+// ---- errors: negative status plus a thread-local message
+int64_t fail(int64_t code, const char *fmt, ...);
+const std::string &last_error();
+
+#define HIPCHK(expr)                                                                                        \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return ::mcm::host::fail(MCM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                                     __LINE__);                                                             \
+    } while (0)
+
+// ---- options (mcm_set_option)
+struct Options {
+    bool apsb = false;        // driver
+    bool wr = true;           // bfs
+    int mapping = 2;          // 0 thread, 1 wave, 2 auto
+    int loop = 2;             // 0 device, 1 host, 2 auto
+    bool validate = false;
+    bool stats = false;
+    std::string tuning;       // autotuner cache file ("" = memory only)
+    bool autotune = false;    // batch plans time the candidate configurations
+    int block = 1024;         // persistent block size
+    int blocks_per_cu = 1;    // 0 = occupancy limit
+    int wg_block = 1024;      // one-workgroup matcher block size
+    int64_t wg_threshold = 16384;  // nc + nr at or below which one workgroup matches alone
+    int64_t small_max = 256;  // frontiers up to this size are expanded by one workgroup
+    int batch_min = 8;        // fewest frontier entries per wavefront batch
+    int split = 64;           // heavier columns enter the frontier in pieces of this many edges (0 = off)
+    double timeout_s = 20.0;  // device barrier wait limit
+};
+Options opts();
+
+// ---- per-device workspace (grow-only, one per device, guarded by workspace_mutex)
+struct DevInfo {
+    int ncu = 0;
+    double clock_khz = 100000.0;
+    std::string arch;
+};
+
+struct Workspace {
+    int device = -1;
+    size_t cap_nc = 0, cap_nr = 0, cap_q = 0;
+    uint64_t *rw = nullptr;
+    int32_t *pred = nullptr;
+    uint32_t *cdone = nullptr;
+    int4 *fq = nullptr;
+    int32_t *ends = nullptr;
+    int32_t *cwork = nullptr;
+    uint32_t *ctrl = nullptr;
+    uint32_t *bar = nullptr;     // grid barrier arrival flags
+    BatchDesc *desc = nullptr;
+    size_t cap_desc = 0;
+    int32_t *order = nullptr;
+    int64_t *card = nullptr;
+    uint32_t *h_ctrl = nullptr;  // pinned
+    BatchDesc *h_desc = nullptr; // pinned
+    int32_t *h_order = nullptr;  // pinned
+    int64_t *h_card = nullptr;   // pinned
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevInfo info;
+};
+
+Workspace &workspace(int dev);
+std::mutex &workspace_mutex();
+int64_t ensure_base(Workspace &w, int dev);
+int64_t ensure_graph(Workspace &w, size_t nc, size_t nr, size_t qcap);
+int64_t ensure_desc(Workspace &w, size_t n);
+int64_t get_device_info(int dev, DevInfo *info);
+
+uint32_t *ctrl_line(uint32_t *ctrl, int l);
+uint64_t ctrl_stat(uint32_t *ctrl, int s);
+RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info);
+uint32_t base_flags(const Options &o, int64_t nc, int64_t nnz_hint);
+int current_device(int *dev);
+void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int loop, uint32_t flags,
+                  double clock_khz);
+
+}  // namespace host
+}  // namespace mcm

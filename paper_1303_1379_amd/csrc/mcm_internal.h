@@ -64,13 +64,24 @@ struct RunOpt {
     uint32_t max_phases;   // watchdog: phases
     uint32_t max_levels;   // watchdog: levels per phase
     uint32_t small_max;    // frontiers up to this size are expanded by one workgroup (0 = never)
+    uint32_t batch_min;    // fewest frontier entries a wavefront takes per batch (1..64)
+    uint32_t split;        // a column with more edges enters the frontier as several entries of at
+                           // most `split` edges each (0 = never; queue capacity must allow it)
     uint64_t timeout;      // wall-clock ticks a grid barrier may wait
 };
 
-// One graph of a batch (same fields as mcm_graph of the C interface).
+// One graph of a batch: device addresses of its inputs, outputs and
+// workspace slices (rw, pred, ends: nr entries; cdone: nc; fq: 2*nc).
 struct BatchDesc {
     int32_t nc, nr;
-    int64_t colptr_off, rowind_off, col_off, row_off;
+    const int32_t *colptr, *rowind;
+    const int32_t *init_c, *init_r;   // null = empty initial matching
+    int32_t *out_c, *out_r;
+    uint64_t *rw;
+    int32_t *pred;
+    uint32_t *cdone;
+    int4 *fq;
+    int32_t *ends;
 };
 
 // Per-wavefront LDS staging of queue pushes.

@@ -261,20 +261,42 @@ struct Acc {
 // Entries per wavefront batch: spread a small frontier so that every busy
 // wavefront gets about one chunk of edges (latency), a large one in full
 // batches of 64 (throughput).
-DEV uint32_t batch_size(uint32_t n, uint32_t nwaves)
+DEV uint32_t batch_size(uint32_t n, uint32_t nwaves, uint32_t bmin)
 {
-    const uint32_t b = (n + nwaves - 1) / nwaves;
+    uint32_t b = (n + nwaves - 1) / nwaves;
+    if (b < bmin) b = bmin;
     return b < 1 ? 1u : (b > 64 ? 64u : b);
+}
+
+// Push frontier entry `e` (column e.x, root e.y, edges [e.z, e.w)); a column
+// with more than `split` edges goes in as consecutive entries of at most
+// `split` edges, so that the edges of one heavy column are expanded by
+// several wavefronts.  Wavefront-uniform call.
+DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, int4 *gq, uint32_t *gcnt)
+{
+    const bool heavy = p && split != 0 && (uint32_t)(e.w - e.z) > split;
+    if (__ballot(heavy) == 0) {
+        stage_push<int4, kStageQ>(p, e, st.q, st.nq, gq, gcnt);
+        return;
+    }
+    const int nch = p ? (heavy ? (int)((e.w - e.z + split - 1) / split) : 1) : 0;
+    const int maxk = wave_max(nch);
+    for (int k = 0; k < maxk; ++k) {
+        const int b = e.z + k * (int)split;
+        const int en = heavy ? min(e.w, b + (int)split) : e.w;
+        stage_push<int4, kStageQ>(k < nch, make_int4(e.x, e.y, b, en), st.q, st.nq, gq, gcnt);
+    }
 }
 
 template <bool WAVE, int S>
 DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
-                      int level, uint32_t flags, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc)
+                      int level, const RunOpt &o, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc)
 {
     const int lane = __lane_id();
+    const uint32_t flags = o.flags;
     const uint64_t t0 = (flags & F_STATS) ? wall_clock64() : 0;
     bool any_end = false;
-    const uint32_t B = batch_size(n, nwaves);
+    const uint32_t B = batch_size(n, nwaves, o.batch_min);
     for (uint32_t base = wave * B; base < n; base += nwaves * B) {
         const uint32_t i = base + lane;
         int4 e = make_int4(0, 0, 0, 0);
@@ -292,16 +314,16 @@ DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wa
             for (int eb = 0; eb < total; eb += 64) {
                 const int k = eb + lane;
                 // owner lane: the largest o with excl[o] <= k (excl is non-decreasing)
-                int o = 0;
+                int own = 0;
 #pragma unroll
                 for (int step = 32; step >= 1; step >>= 1) {
-                    const int v = __shfl(excl, o + step, 64);
-                    if (v <= k) o += step;
+                    const int v = __shfl(excl, own + step, 64);
+                    if (v <= k) own += step;
                 }
-                const int ocol = __shfl(e.x, o, 64);
-                const int oroot = __shfl(e.y, o, 64);
-                const int obeg = __shfl(e.z, o, 64);
-                const int oexcl = __shfl(excl, o, 64);
+                const int ocol = __shfl(e.x, own, 64);
+                const int oroot = __shfl(e.y, own, 64);
+                const int obeg = __shfl(e.z, own, 64);
+                const int oexcl = __shfl(excl, own, 64);
                 bool newcol = false, newend = false;
                 int4 ne = make_int4(0, 0, 0, 0);
                 int r = 0;
@@ -309,7 +331,7 @@ DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wa
                     r = g.rowind[obeg + (k - oexcl)];
                     visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend);
                 }
-                stage_push<int4, kStageQ>(newcol, ne, st.q, st.nq, io.nfq, io.ncnt);
+                push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
                 stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt);
                 any_end |= newend;
                 if (flags & F_STATS) { acc.claimed += newcol; acc.found += newend; }
@@ -324,7 +346,7 @@ DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wa
                     r = g.rowind[e.z + t];
                     visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend);
                 }
-                stage_push<int4, kStageQ>(newcol, ne, st.q, st.nq, io.nfq, io.ncnt);
+                push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
                 stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt);
                 any_end |= newend;
                 if (flags & F_STATS) { acc.claimed += newcol; acc.found += newend; }
@@ -342,10 +364,11 @@ DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wa
 // root and an entry of the first frontier.  Columns without edges can never
 // be matched and would expand nothing.  Every thread of the workgroup calls
 // it.
-DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, uint32_t flags, uint32_t *cnt, Stage &st,
+DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const RunOpt &o, uint32_t *cnt, Stage &st,
                     uint32_t *s_tmp, Acc &acc)
 {
     const int lane = __lane_id();
+    const uint32_t flags = o.flags;
     for (uint32_t base = wave * 64u; base < (uint32_t)g.nc; base += nwaves * 64u) {
         const int c = (int)(base + lane);
         bool p = false;
@@ -359,7 +382,7 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, uint32_t 
             if (flags & F_LEVELS) g.clevel[c] = un ? 0 : -1;
         }
         if (flags & F_STATS) acc.roots += p;
-        stage_push<int4, kStageQ>(p, e, st.q, st.nq, g.fq0, cnt);
+        push_entry(p, e, o.split, st, g.fq0, cnt);
     }
     block_flush(st, g.fq0, cnt, g.ends, nullptr, s_tmp);
 }
@@ -490,7 +513,7 @@ DEV uint32_t small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, ui
         __syncthreads();
         const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
         LevelIO io{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], &s_loc[4], &s_loc[3]};
-        expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, flags, io, st, s_tmp, acc);
+        expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
         ++levels;
         if ((flags & F_APSB) && *(volatile uint32_t *)&s_loc[3]) { stop = 1; break; }
         ++L;
@@ -533,7 +556,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     };
     for (;; ++ph) {
         if (ph > o.max_phases) { if (leader) set_status(ctrl, kEInternal); return false; }
-        init_roots(g, wave, nwaves, flags, fc(0), st, s_tmp, acc);
+        init_roots(g, wave, nwaves, o, fc(0), st, s_tmp, acc);
         if (!sync()) return false;
         int L = 0;
         for (;;) {
@@ -554,7 +577,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             if (leader) { *fc((L + 2) % 3) = 0; *fd((L + 2) % 3) = 0; }
             const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
             LevelIO io{(L & 1) ? g.fq0 : g.fq1, fc((L + 1) % 3), line(ctrl, L_NENDS), fd(L % 3)};
-            expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, flags, io, st, s_tmp, acc);
+            expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
             ++total_levels;
             if (!sync()) return false;
             if ((flags & F_APSB) && ld_u<kAgent>(fd(L % 3)) != 0) break;
@@ -592,7 +615,7 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint64_t 
         __syncthreads();
         if (threadIdx.x == 0) for (int i = 0; i < 5; ++i) s_loc[i] = 0;
         __syncthreads();
-        init_roots(g, wave, nwaves, flags, &s_loc[0], st, s_tmp, acc);
+        init_roots(g, wave, nwaves, o, &s_loc[0], st, s_tmp, acc);
         int L = 0;
         for (;;) {
             const uint32_t n = *(volatile uint32_t *)&s_loc[L % 3];
@@ -603,7 +626,7 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint64_t 
             __syncthreads();
             const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
             LevelIO io{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], &s_loc[4], &s_loc[3]};
-            expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, flags, io, st, s_tmp, acc);
+            expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
             ++total_levels;
             if ((flags & F_APSB) && *(volatile uint32_t *)&s_loc[3]) break;
             ++L;
@@ -694,19 +717,21 @@ __global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl,
 }
 
 // Host-driven steps (one launch each).
-__global__ void k_init_roots(DevGraph g, uint32_t *ctrl, uint32_t flags)
+__global__ void k_init_roots(DevGraph g, uint32_t *ctrl, RunOpt o)
 {
     extern __shared__ __align__(16) char smem[];
     Stage st = make_stage(smem);
+    const uint32_t flags = o.flags;
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nwaves = gridDim.x * (blockDim.x >> 6);
     Acc acc;
-    init_roots(g, wave, nwaves, flags, line(ctrl, L_FCOUNT0), st, stage_tmp(smem), acc);
+    init_roots(g, wave, nwaves, o, line(ctrl, L_FCOUNT0), st, stage_tmp(smem), acc);
     if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0))); }
 }
 
 template <bool WAVE>
-__global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint32_t n, uint32_t ph, int L, uint32_t flags)
+__global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint32_t n, uint32_t ph, int L, RunOpt o)
 {
+    const uint32_t flags = o.flags;
     extern __shared__ __align__(16) char smem[];
     Stage st = make_stage(smem);
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nwaves = gridDim.x * (blockDim.x >> 6);
@@ -718,7 +743,7 @@ __global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint
     LevelIO io{(L & 1) ? g.fq0 : g.fq1, line(ctrl, L_FCOUNT0 + (L + 1) % 3), line(ctrl, L_NENDS),
                line(ctrl, L_FOUND0 + L % 3)};
     Acc acc;
-    expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, flags, io, st, stage_tmp(smem), acc);
+    expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
     if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0))); }
 }
 
@@ -795,10 +820,6 @@ __global__ void k_zero_ctrl(uint32_t *ctrl)
 // it is empty.  Every graph gets its own state slices; counters live in LDS.
 template <bool WAVE>
 __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const int32_t *order, int32_t ngraphs,
-                                                   const int32_t *colptr_all, const int32_t *rowind_all,
-                                                   const int32_t *init_c, const int32_t *init_r, int32_t *cmatch_all,
-                                                   int32_t *out_r, uint64_t *rw_all, int32_t *pred_all,
-                                                   uint32_t *cdone_all, int4 *fq_all, int32_t *ends_all,
                                                    int64_t *card, uint32_t *ctrl, RunOpt o)
 {
     extern __shared__ __align__(16) char smem[];
@@ -818,31 +839,31 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
         const int32_t gi = order ? order[qi] : qi;
         const BatchDesc d = descs[gi];
         DevGraph g;
-        g.colptr = colptr_all + d.colptr_off;
-        g.rowind = rowind_all + d.rowind_off;
+        g.colptr = d.colptr;
+        g.rowind = d.rowind;
         g.nc = d.nc;
         g.nr = d.nr;
-        g.cmatch = cmatch_all + d.col_off;
-        g.rw = rw_all + d.row_off;
-        g.pred = pred_all + d.row_off;
-        g.cdone = cdone_all + d.col_off;
-        g.fq0 = fq_all + 2 * d.col_off;
-        g.fq1 = fq_all + 2 * d.col_off + d.nc;
-        g.ends = ends_all + d.row_off;
+        g.cmatch = d.out_c;
+        g.rw = d.rw;
+        g.pred = d.pred;
+        g.cdone = d.cdone;
+        g.fq0 = d.fq;
+        g.fq1 = d.fq + d.nc;
+        g.ends = d.ends;
         g.clevel = nullptr;
         for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
-            g.cmatch[c] = init_c ? init_c[d.col_off + c] : -1;
+            g.cmatch[c] = d.init_c ? d.init_c[c] : -1;
             g.cdone[c] = 0;
         }
         for (int r = threadIdx.x; r < g.nr; r += blockDim.x)
-            g.rw[r] = (uint64_t)(uint32_t)(init_r ? init_r[d.row_off + r] : -1);
+            g.rw[r] = (uint64_t)(uint32_t)(d.init_r ? d.init_r[r] : -1);
         if (threadIdx.x == 0) s_m = 0;
         __syncthreads();
         uint32_t ph = 0, lv = 0;
         const bool ok = (g.nc > 0 && g.nr > 0) ? run_block<WAVE>(g, ctrl, o, stats, st, s_tmp, s_loc, &ph, &lv) : true;
         __syncthreads();
         uint32_t m = 0;
-        for (int r = threadIdx.x; r < g.nr; r += blockDim.x) out_r[d.row_off + r] = (int32_t)(uint32_t)g.rw[r];
+        for (int r = threadIdx.x; r < g.nr; r += blockDim.x) d.out_r[r] = (int32_t)(uint32_t)g.rw[r];
         for (int c = threadIdx.x; c < g.nc; c += blockDim.x) m += (g.cmatch[c] >= 0);
         if (m) atomicAdd(&s_m, m);
         __syncthreads();
@@ -853,6 +874,43 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
             atomicAdd(line(ctrl, L_LEVELS), lv);
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------
+// Device-side cheap initial matching (the paper initialises every run with
+// a cheap greedy matching, section 4).  Parallel form: every column scans
+// its rows in stored order and takes the first one it can move from -1 to
+// itself with a compare-and-swap.  An unmatched column ends with all its
+// rows matched, so the result is a maximal matching; which one depends on
+// the schedule, unlike the sequential greedy of mcm_cheap_init_host.
+__global__ void k_unmatch_all(const BatchDesc *descs, int32_t ngraphs)
+{
+    for (int32_t gi = blockIdx.y; gi < ngraphs; gi += gridDim.y) {
+        const BatchDesc d = descs[gi];
+        const int32_t n = d.nc > d.nr ? d.nc : d.nr;
+        for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            if (i < d.nc) d.out_c[i] = -1;
+            if (i < d.nr) d.out_r[i] = -1;
+        }
+    }
+}
+
+__global__ void k_cheap_init(const BatchDesc *descs, int32_t ngraphs)
+{
+    for (int32_t gi = blockIdx.y; gi < ngraphs; gi += gridDim.y) {
+        const BatchDesc d = descs[gi];
+        for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < d.nc; c += gridDim.x * blockDim.x) {
+            const int32_t e = d.colptr[c + 1];
+            for (int32_t j = d.colptr[c]; j < e; ++j) {
+                const int32_t r = d.rowind[j];
+                if (d.out_r[r] != -1) continue;
+                if (atomicCAS(&d.out_r[r], -1, c) == -1) {
+                    d.out_c[c] = r;
+                    break;
+                }
+            }
+        }
     }
 }
 
@@ -918,21 +976,22 @@ hipError_t launch_persistent(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, c
                                       (unsigned)stage_lds_bytes(block / 64), st);
 }
 
-hipError_t launch_init_roots(const DevGraph &g, uint32_t *ctrl, uint32_t flags, hipStream_t st)
+hipError_t launch_init_roots(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, hipStream_t st)
 {
     hipLaunchKernelGGL(k_init_roots, dim3(clamp_blocks(g.nc, 256, 1, 4096)), dim3(256), stage_lds_bytes(4), st, g,
-                       ctrl, flags);
+                       ctrl, o);
     return hipGetLastError();
 }
 
-hipError_t launch_level(const DevGraph &g, uint32_t *ctrl, uint32_t n, uint32_t ph, int L, uint32_t flags, bool wave,
+hipError_t launch_level(const DevGraph &g, uint32_t *ctrl, uint32_t n, uint32_t ph, int L, const RunOpt &o, bool wave,
                         int max_blocks, hipStream_t st)
 {
-    const int blocks = clamp_blocks(n, 4, 1, max_blocks);  // about one entry per wavefront when n is small
+    // about batch_min entries per wavefront when n is small
+    const int blocks = clamp_blocks(n, 4 * (int)(o.batch_min ? o.batch_min : 1), 1, max_blocks);
     if (wave)
-        hipLaunchKernelGGL(k_level<true>, dim3(blocks), dim3(256), stage_lds_bytes(4), st, g, ctrl, n, ph, L, flags);
+        hipLaunchKernelGGL(k_level<true>, dim3(blocks), dim3(256), stage_lds_bytes(4), st, g, ctrl, n, ph, L, o);
     else
-        hipLaunchKernelGGL(k_level<false>, dim3(blocks), dim3(256), stage_lds_bytes(4), st, g, ctrl, n, ph, L, flags);
+        hipLaunchKernelGGL(k_level<false>, dim3(blocks), dim3(256), stage_lds_bytes(4), st, g, ctrl, n, ph, L, o);
     return hipGetLastError();
 }
 
@@ -968,21 +1027,41 @@ hipError_t launch_export_pred(const DevGraph &g, uint32_t ph, int32_t *row_pred,
     return hipGetLastError();
 }
 
-hipError_t launch_match_wg(const BatchDesc *descs, const int32_t *order, int32_t ngraphs, const int32_t *cp,
-                           const int32_t *ri, const int32_t *ic, const int32_t *ir, int32_t *cm, int32_t *out_r,
-                           uint64_t *rw, int32_t *pred, uint32_t *cdone, int4 *fq, int32_t *ends, int64_t *card,
+hipError_t launch_match_wg(const BatchDesc *descs, const int32_t *order, int32_t ngraphs, int64_t *card,
                            uint32_t *ctrl, const RunOpt &o, bool wave, int blocks, int block, hipStream_t st)
 {
     const int lds = stage_lds_bytes(block / 64);
-    const void *fn = wave ? reinterpret_cast<const void *>(&k_match_wg<true>) : reinterpret_cast<const void *>(&k_match_wg<false>);
-    hipError_t e = allow_lds(fn, lds);
-    if (e != hipSuccess) return e;
     if (wave)
-        hipLaunchKernelGGL(k_match_wg<true>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, cp, ri, ic, ir,
-                           cm, out_r, rw, pred, cdone, fq, ends, card, ctrl, o);
+        hipLaunchKernelGGL(k_match_wg<true>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, card, ctrl, o);
     else
-        hipLaunchKernelGGL(k_match_wg<false>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, cp, ri, ic,
-                           ir, cm, out_r, rw, pred, cdone, fq, ends, card, ctrl, o);
+        hipLaunchKernelGGL(k_match_wg<false>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, card, ctrl, o);
+    return hipGetLastError();
+}
+
+// Raise the dynamic-LDS limit of the one-workgroup kernel (outside any
+// stream capture).
+hipError_t prepare_match_wg(int block)
+{
+    const int lds = stage_lds_bytes(block / 64);
+    hipError_t e = allow_lds(reinterpret_cast<const void *>(&k_match_wg<true>), lds);
+    if (e != hipSuccess) return e;
+    return allow_lds(reinterpret_cast<const void *>(&k_match_wg<false>), lds);
+}
+
+// Occupancy of the one-workgroup kernel (blocks per CU).
+hipError_t match_wg_occupancy(bool wave, int block, int *per_cu)
+{
+    const void *fn = wave ? reinterpret_cast<const void *>(&k_match_wg<true>) : reinterpret_cast<const void *>(&k_match_wg<false>);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, block, stage_lds_bytes(block / 64));
+}
+
+hipError_t launch_cheap_init(const BatchDesc *descs, int32_t ngraphs, hipStream_t st)
+{
+    const dim3 grid(256, (unsigned)(ngraphs < 65535 ? ngraphs : 65535));
+    hipLaunchKernelGGL(k_unmatch_all, grid, dim3(256), 0, st, descs, ngraphs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cheap_init, grid, dim3(256), 0, st, descs, ngraphs);
     return hipGetLastError();
 }
 

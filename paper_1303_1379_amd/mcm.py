@@ -48,7 +48,9 @@ class mcm_stats(ctypes.Structure):
 
 
 EXPORTS = ["mcm_match", "mcm_match_batched", "mcm_konig_cover", "mcm_bfs_levels", "mcm_cheap_init_host",
-           "mcm_set_option", "mcm_get_option", "mcm_last_stats", "mcm_strerror", "mcm_version"]
+           "mcm_cheap_init", "mcm_batch_plan_create", "mcm_batch_plan_run", "mcm_batch_plan_info",
+           "mcm_batch_plan_destroy", "mcm_set_option", "mcm_get_option", "mcm_last_stats", "mcm_strerror",
+           "mcm_version"]
 
 _lib = None
 
@@ -72,6 +74,17 @@ def lib():
     L.mcm_bfs_levels.restype = i64
     L.mcm_cheap_init_host.argtypes = [i32, i32, vp, vp, vp, vp]
     L.mcm_cheap_init_host.restype = i64
+    L.mcm_cheap_init.argtypes = [i32, i32, vp, vp, vp, vp, vp]
+    L.mcm_cheap_init.restype = i64
+    L.mcm_batch_plan_create.argtypes = [i32, ctypes.POINTER(mcm_graph), vp, vp, vp, vp, vp, vp,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+    L.mcm_batch_plan_create.restype = i64
+    L.mcm_batch_plan_run.argtypes = [vp, vp, vp]
+    L.mcm_batch_plan_run.restype = i64
+    L.mcm_batch_plan_info.argtypes = [vp, ctypes.c_char_p, i32]
+    L.mcm_batch_plan_info.restype = ctypes.c_int
+    L.mcm_batch_plan_destroy.argtypes = [vp]
+    L.mcm_batch_plan_destroy.restype = ctypes.c_int
     L.mcm_set_option.argtypes = [ctypes.c_char_p, ctypes.c_char_p]
     L.mcm_set_option.restype = ctypes.c_int
     L.mcm_get_option.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i32]
@@ -262,3 +275,56 @@ def match_batched(b: DeviceBatch, init_cmatch=None, init_rmatch=None, out_cmatch
                                            _ptr(init_rmatch), _ptr(out_cmatch), _ptr(out_rmatch),
                                            card.ctypes.data, _stream(stream)))
     return total, card[: b.ngraphs], out_cmatch, out_rmatch
+
+
+def cheap_init(dg: DeviceGraph, stream=None):
+    """mcm_cheap_init (device parallel greedy); returns (|M0|, cmatch, rmatch)."""
+    import torch
+    dev = dg.colptr.device
+    cm = torch.empty(dg.nc, dtype=torch.int32, device=dev)
+    rm = torch.empty(dg.nr, dtype=torch.int32, device=dev)
+    card = _check(lib().mcm_cheap_init(dg.nc, dg.nr, _ptr(dg.colptr), _ptr(dg.rowind), _ptr(cm), _ptr(rm),
+                                       _stream(stream)))
+    return card, cm, rm
+
+
+class BatchPlan:
+    """mcm_batch_plan_*: a captured, replayable batched match over fixed arrays."""
+
+    def __init__(self, b: DeviceBatch, init_cmatch=None, init_rmatch=None, out_cmatch=None, out_rmatch=None):
+        import torch
+        dev = b.colptr.device
+        self.batch = b
+        self.init_cmatch, self.init_rmatch = init_cmatch, init_rmatch
+        self.out_cmatch = out_cmatch if out_cmatch is not None else torch.empty(max(b.ncol_total, 1),
+                                                                                dtype=torch.int32, device=dev)
+        self.out_rmatch = out_rmatch if out_rmatch is not None else torch.empty(max(b.nrow_total, 1),
+                                                                                dtype=torch.int32, device=dev)
+        h = ctypes.c_void_p()
+        _check(lib().mcm_batch_plan_create(b.ngraphs, b.descs, _ptr(b.colptr), _ptr(b.rowind), _ptr(init_cmatch),
+                                           _ptr(init_rmatch), _ptr(self.out_cmatch), _ptr(self.out_rmatch),
+                                           ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        card = np.zeros(max(self.batch.ngraphs, 1), np.int64)
+        total = _check(lib().mcm_batch_plan_run(self._h, card.ctypes.data, _stream(stream)))
+        return total, card[: self.batch.ngraphs]
+
+    def info(self) -> dict:
+        import json
+        buf = ctypes.create_string_buffer(1024)
+        _check(lib().mcm_batch_plan_info(self._h, buf, 1024))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self._h:
+            lib().mcm_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

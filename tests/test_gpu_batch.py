@@ -1,0 +1,119 @@
+"""Batched matching through the C ABI: captured batch plans, the autotuner,
+and the device-side cheap initial matching, all checked against the CPU
+oracle (exact cardinalities, valid matchings)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_1303_1379_amd import graphgen as gg, mcm  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _reset():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    defaults = dict(mapping="auto", autotune=0, tuning="", stats=0, wg_block=1024, batch_min=8)
+    for k, v in defaults.items():
+        mcm.set_option(k, v)
+    yield
+    for k, v in defaults.items():
+        mcm.set_option(k, v)
+
+
+def _batch(n, hi=4096, seed=4):
+    graphs = [gg.batch_member(seed, i, hi=hi) for i in range(n)]
+    inits = [mcm.cheap_init_host(g.colptr, g.rowind, g.nr) for g in graphs]
+    b = mcm.pack_batch(graphs)
+    icm = torch.from_numpy(np.concatenate([x[1] for x in inits])).cuda()
+    irm = torch.from_numpy(np.concatenate([x[2] for x in inits])).cuda()
+    refs = [O.hopcroft_karp(g, *O.cheap_init(g))[0] for g in graphs]
+    return graphs, b, icm, irm, refs
+
+
+def _check_outputs(graphs, cm, rm, cards):
+    cmh, rmh = cm.cpu().numpy(), rm.cpu().numpy()
+    co = ro = 0
+    for i, g in enumerate(graphs):
+        assert O.check_matching(g, cmh[co:co + g.nc], rmh[ro:ro + g.nr]) == cards[i], i
+        co += g.nc
+        ro += g.nr
+
+
+def test_plan_replays_match_eager_and_oracle():
+    graphs, b, icm, irm, refs = _batch(160)
+    total_e, cards_e, cm_e, rm_e = mcm.match_batched(b, icm, irm)
+    assert cards_e.tolist() == refs
+    plan = mcm.BatchPlan(b, icm, irm)
+    single = gg.workload("grid128")
+    dgs = mcm.to_device(single)
+    for rep in range(4):
+        total, cards = plan.run()
+        torch.cuda.synchronize()
+        assert total == total_e and cards.tolist() == refs, rep
+        _check_outputs(graphs, plan.out_cmatch, plan.out_rmatch, cards)
+        # the program's own eager work between replays
+        mcm.match(dgs)
+        mcm.match_batched(b, icm, irm)
+        torch.cuda.synchronize()
+    info = plan.info()
+    assert info["ngraphs"] == 160 and info["mapping"] in ("wave", "thread")
+    plan.close()
+
+
+def test_plan_sees_new_contents_of_bound_arrays():
+    graphs, b, icm, irm, refs = _batch(40)
+    init_c = icm.clone()
+    init_r = irm.clone()
+    plan = mcm.BatchPlan(b, init_c, init_r)
+    assert plan.run()[1].tolist() == refs
+    # empty initial matching written into the bound arrays: same maximum
+    init_c.fill_(-1)
+    init_r.fill_(-1)
+    torch.cuda.synchronize()
+    total, cards = plan.run()
+    assert cards.tolist() == refs
+    _check_outputs(graphs, plan.out_cmatch, plan.out_rmatch, cards)
+    plan.close()
+
+
+def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
+    path = str(tmp_path / "tune.jsonl")
+    mcm.set_option("tuning", path)
+    mcm.set_option("autotune", 1)
+    graphs, b, icm, irm, refs = _batch(96)
+    plan = mcm.BatchPlan(b, icm, irm)
+    info = plan.info()
+    assert info["tuned"] and info["tuned_ms"] > 0
+    assert info["block"] in (256, 512, 1024) and info["batch_min"] in (1, 8, 32)
+    assert plan.run()[1].tolist() == refs
+    plan.close()
+    lines = [json.loads(x) for x in open(path).read().splitlines() if x.strip()]
+    assert any(x["key"] == info["key"] for x in lines)
+    # a later plan of the same size class reuses the cached choice without timing
+    mcm.set_option("autotune", 0)
+    plan2 = mcm.BatchPlan(b, icm, irm)
+    i2 = plan2.info()
+    assert i2["tuned"] and i2["block"] == info["block"] and i2["mapping"] == info["mapping"]
+    assert plan2.run()[1].tolist() == refs
+    plan2.close()
+    # one-shot batched matching also picks up the cached configuration
+    assert mcm.match_batched(b, icm, irm)[1].tolist() == refs
+
+
+@pytest.mark.parametrize("name", ["uniform2000", "grid128", "rmat14"])
+def test_device_cheap_init_is_maximal(name):
+    g = gg.workload(name)
+    dg = mcm.to_device(g)
+    card0, cm, rm = mcm.cheap_init(dg)
+    cmh, rmh = cm.cpu().numpy(), rm.cpu().numpy()
+    assert O.check_matching(g, cmh, rmh) == card0
+    cols, rows = g.edges()
+    assert not np.any((cmh[cols] == -1) & (rmh[rows] == -1)), "not maximal"
+    card, _, _ = mcm.match(dg, cm, rm)
+    assert card == O.hopcroft_karp(g, *O.cheap_init(g))[0]
