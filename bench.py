@@ -81,6 +81,71 @@ def cpu_baseline(g, cm0, rm0, budget_s):
             "phases": s["phases"], "seconds": round(s["seconds"], 3)}
 
 
+def bench_batched(ngraphs, steps):
+    """Uneven batch (graph g: seed mix(4, g), sizes log-uniform in [64, 65536],
+    degrees 2..12, half uniform / half banded, 2 % columns emptied): one
+    batched launch (autotuned, hipGraph-captured plan) vs a per-graph loop of
+    mcm_match on the same resident inputs; per-graph |M| must be identical."""
+    import numpy as np
+    import torch
+    from paper_1303_1379_amd import graphgen as gg, mcm
+    t0 = time.time()
+    graphs = [gg.batch_member(4, i) for i in range(ngraphs)]
+    t_gen = time.time() - t0
+    inits = [mcm.cheap_init_host(g.colptr, g.rowind, g.nr) for g in graphs]
+    b = mcm.pack_batch(graphs)
+    icm = torch.from_numpy(np.concatenate([x[1] for x in inits])).cuda()
+    irm = torch.from_numpy(np.concatenate([x[2] for x in inits])).cuda()
+    mcm.set_option("autotune", 1)
+    plan = mcm.BatchPlan(b, icm, irm)
+    mcm.set_option("autotune", 0)
+    plan.run()
+    ts = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        total, cards = plan.run()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    dgs = [mcm.to_device(g) for g in graphs]
+    oc = np.cumsum([0] + [g.nc for g in graphs])
+    orr = np.cumsum([0] + [g.nr for g in graphs])
+    mcm.match(dgs[0], icm[0:oc[1]], irm[0:orr[1]])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    loop_cards = [mcm.match(dg, icm[oc[i]:oc[i + 1]], irm[orr[i]:orr[i + 1]])[0] for i, dg in enumerate(dgs)]
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t
+    t_b = float(np.median(ts))
+    return {"workload": f"{ngraphs} uneven graphs (sizes log-uniform 64..65536, degree 2..12, half uniform / half "
+                        "banded, 2% columns emptied), greedy initial matchings",
+            "sum_cols": int(sum(g.nc for g in graphs)), "sum_nnz": int(sum(g.nnz for g in graphs)),
+            "batched_graphs_per_s": round(ngraphs / t_b, 1), "batched_ms": round(t_b * 1000, 3),
+            "loop_graphs_per_s": round(ngraphs / t_loop, 1), "loop_ms": round(t_loop * 1000, 3),
+            "ratio": round(t_loop / t_b, 2), "identical_cardinalities": loop_cards == cards.tolist(),
+            "plan": plan.info(), "generate_s": round(t_gen, 2)}
+
+
+def bench_serving(pool_size, nreq, warmup, lam):
+    """Poisson arrivals through the continuous-batching server (64 GB HBM
+    budget); requests drawn from a pool of distinct graphs of the serving mix
+    (n log-uniform 1e3..1e6 per side, degree 4..16, half uniform, half R-MAT)."""
+    from paper_1303_1379_amd import mcm, serving
+    t0 = time.time()
+    pool = serving.make_pool(pool_size, seed=5)
+    t_gen = time.time() - t0
+    srv = mcm.Server(64 << 30, max_batch=1024)
+    r = serving.replay(srv, pool, nreq, lam=lam, seed=6, warmup=warmup)
+    st = srv.stats()
+    srv.close()
+    r.update({"pool_graphs": pool_size, "pool_mean_n": round(sum(g.nc for g, _, _ in pool) / pool_size, 1),
+              "pool_mean_nnz": round(sum(g.nnz for g, _, _ in pool) / pool_size, 1), "budget_bytes": 64 << 30,
+              "peak_bytes": st["peak_bytes"], "launches_batched": st["launches_batched"],
+              "launches_whole_device": st["launches_grid"], "max_batch": st["max_batch_seen"],
+              "generate_s": round(t_gen, 2)})
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +155,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-stats", action="store_true", help="skip the untimed counter run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of matching, copy this many bytes with a plain device copy (counter calibration)")
     args = ap.parse_args()
@@ -190,6 +259,10 @@ def main():
         out["block0_ms"] = {k: round(stats[k], 2) for k in ("t_expand_ms", "t_flush_ms", "t_barrier_ms",
                                                              "t_small_ms", "t_augment_ms")}
     out["setup_s"] = {"generate": round(t_gen, 2)}
+    if not args.no_batched:
+        out["batched"] = bench_batched(args.batch_graphs, max(args.steps, 3))
+    if not args.no_serving:
+        out["serving"] = bench_serving(48, args.serve_requests, args.serve_requests // 8, 2000.0)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, cm0, rm0, args.cpu_budget)
         out["cpu_baseline"]["cores"] = 1

@@ -169,6 +169,59 @@ int64_t mcm_cheap_init(int32_t ncols, int32_t nrows, const int32_t *colptr, cons
                        int32_t *cmatch, int32_t *rmatch, void *stream);
 
 /*
+ * Serving: a continuous-batching request server.  Requests (one graph each,
+ * HOST CSC arrays) are admitted in arrival order while their device
+ * footprint (inputs, outputs and workspace, about 4(nc+1) + 4 nnz + 12 nc +
+ * 28 nr bytes plus queue space) fits the HBM budget; later requests wait in
+ * the queue until memory returns.  A worker thread copies admitted inputs
+ * to the device on a copy stream and keeps launching the batched matcher
+ * over every admitted request whose inputs have arrived, while new requests
+ * are admitted and copied; requests with nc + nr above a threshold
+ * (max(wg_threshold, 2^17)) are matched by the whole device between
+ * batches.  Every request starts from the device cheap matching and ends
+ * with a maximum matching of its graph, copied back into the caller's
+ * arrays; its memory is then released.
+ *
+ *   mcm_server_create  budget in bytes (> 0), largest batch per launch (>= 1)
+ *   mcm_server_submit  colptr[ncols+1], rowind[nnz]: HOST inputs;
+ *                      cmatch[ncols], rmatch[nrows]: HOST outputs.  All four
+ *                      must stay valid until the request is polled done
+ *                      (pinned memory makes the copies asynchronous).
+ *                      Returns a ticket > 0, MCM_ENOMEM if the request alone
+ *                      exceeds the budget, MCM_EINVAL for bad arguments.
+ *   mcm_server_poll    waits up to wait_ms (0 = no wait) for the ticket;
+ *                      returns 1 (done: outputs written, *info filled, the
+ *                      ticket is released), 0 (not yet) or a negative status
+ *   mcm_server_stats_get  counters of the server
+ *   mcm_server_destroy    stops the worker; outstanding requests are dropped
+ * Times in mcm_request_info are milliseconds since the server was created.
+ */
+typedef struct mcm_server mcm_server;
+
+typedef struct {
+    int64_t card;        /* |M| */
+    double submit_ms;    /* request submitted */
+    double admit_ms;     /* memory granted, input copy started */
+    double start_ms;     /* its launch was queued */
+    double done_ms;      /* results on the host */
+    int32_t path;        /* 0 batched launch (one workgroup), 1 whole device */
+    int32_t batch_size;  /* requests in the same launch */
+} mcm_request_info;
+
+typedef struct {
+    int64_t submitted, completed, rejected, queued, in_flight;
+    int64_t bytes_in_use, peak_bytes, budget_bytes;
+    int64_t launches_batched, launches_grid, max_batch_seen;
+} mcm_server_stats;
+
+int64_t mcm_server_create(int64_t hbm_budget_bytes, int32_t max_batch, mcm_server **server);
+int64_t mcm_server_submit(mcm_server *server, int32_t ncols, int32_t nrows, const int32_t *colptr,
+                          const int32_t *rowind, int32_t *cmatch, int32_t *rmatch);
+int64_t mcm_server_poll(mcm_server *server, int64_t ticket, mcm_request_info *info, double wait_ms);
+int mcm_server_stats_get(mcm_server *server, mcm_server_stats *out);
+int mcm_server_destroy(mcm_server *server);
+
+/*
  * mcm_konig_cover -- minimum vertex cover certifying a maximum matching
  * (Konig's theorem; section 2 states the Berge criterion it rests on).
  * Runs one complete alternating BFS from every unmatched column (GPUBFS,

@@ -16,7 +16,7 @@ MCM_LIB = os.path.join(HERE, "libmcm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 HIP_SOURCES = ["mcm_kernels.hip"]
-HOST_SOURCES = ["mcm_api.cpp", "mcm_batch.cpp"]
+HOST_SOURCES = ["mcm_api.cpp", "mcm_batch.cpp", "mcm_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # gfx950 only; packed-FP32 instructions are disabled for every HIP object.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-fno-strict-aliasing",

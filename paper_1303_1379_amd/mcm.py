@@ -37,6 +37,18 @@ class mcm_graph(ctypes.Structure):
                 ("rowind_off", ctypes.c_int64), ("col_off", ctypes.c_int64), ("row_off", ctypes.c_int64)]
 
 
+class mcm_request_info(ctypes.Structure):
+    _fields_ = [("card", ctypes.c_int64), ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double),
+                ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double), ("path", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32)]
+
+
+class mcm_server_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "completed", "rejected", "queued", "in_flight",
+                                              "bytes_in_use", "peak_bytes", "budget_bytes", "launches_batched",
+                                              "launches_grid", "max_batch_seen")]
+
+
 class mcm_stats(ctypes.Structure):
     _fields_ = [("phases", ctypes.c_int64), ("levels", ctypes.c_int64), ("edges_scanned", ctypes.c_int64),
                 ("cols_expanded", ctypes.c_int64), ("cols_claimed", ctypes.c_int64), ("rows_found", ctypes.c_int64),
@@ -49,8 +61,9 @@ class mcm_stats(ctypes.Structure):
 
 EXPORTS = ["mcm_match", "mcm_match_batched", "mcm_konig_cover", "mcm_bfs_levels", "mcm_cheap_init_host",
            "mcm_cheap_init", "mcm_batch_plan_create", "mcm_batch_plan_run", "mcm_batch_plan_info",
-           "mcm_batch_plan_destroy", "mcm_set_option", "mcm_get_option", "mcm_last_stats", "mcm_strerror",
-           "mcm_version"]
+           "mcm_batch_plan_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
+           "mcm_server_stats_get", "mcm_server_destroy", "mcm_set_option", "mcm_get_option", "mcm_last_stats",
+           "mcm_strerror", "mcm_version"]
 
 _lib = None
 
@@ -85,6 +98,16 @@ def lib():
     L.mcm_batch_plan_info.restype = ctypes.c_int
     L.mcm_batch_plan_destroy.argtypes = [vp]
     L.mcm_batch_plan_destroy.restype = ctypes.c_int
+    L.mcm_server_create.argtypes = [i64, i32, ctypes.POINTER(ctypes.c_void_p)]
+    L.mcm_server_create.restype = i64
+    L.mcm_server_submit.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.mcm_server_submit.restype = i64
+    L.mcm_server_poll.argtypes = [vp, i64, ctypes.POINTER(mcm_request_info), ctypes.c_double]
+    L.mcm_server_poll.restype = i64
+    L.mcm_server_stats_get.argtypes = [vp, ctypes.POINTER(mcm_server_stats)]
+    L.mcm_server_stats_get.restype = ctypes.c_int
+    L.mcm_server_destroy.argtypes = [vp]
+    L.mcm_server_destroy.restype = ctypes.c_int
     L.mcm_set_option.argtypes = [ctypes.c_char_p, ctypes.c_char_p]
     L.mcm_set_option.restype = ctypes.c_int
     L.mcm_get_option.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i32]
@@ -321,6 +344,61 @@ class BatchPlan:
         if self._h:
             lib().mcm_batch_plan_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """mcm_server_*: continuous-batching matching server on the current device.
+
+    submit() copies a host graph into pinned buffers the server reads from
+    (kept alive here until the request is polled done) and returns a ticket;
+    poll() returns None while the request is in flight, else (card, info,
+    cmatch, rmatch) with the outputs as numpy arrays."""
+
+    def __init__(self, budget_bytes: int, max_batch: int = 1024):
+        h = ctypes.c_void_p()
+        _check(lib().mcm_server_create(int(budget_bytes), int(max_batch), ctypes.byref(h)))
+        self._h = h
+        self._bufs = {}
+
+    def submit(self, g) -> int:
+        import torch
+        cp = torch.from_numpy(np.ascontiguousarray(g.colptr, dtype=np.int32)).pin_memory()
+        ri = torch.from_numpy(np.ascontiguousarray(g.rowind, dtype=np.int32)).pin_memory()
+        cm = torch.empty(int(g.nc), dtype=torch.int32).pin_memory()
+        rm = torch.empty(int(g.nr), dtype=torch.int32).pin_memory()
+        return self.submit_pinned(int(g.nc), int(g.nr), cp, ri, cm, rm)
+
+    def submit_pinned(self, nc, nr, cp, ri, cm, rm) -> int:
+        """Submit already pinned host tensors (kept referenced until done)."""
+        t = _check(lib().mcm_server_submit(self._h, nc, nr, _ptr(cp), _ptr(ri), _ptr(cm), _ptr(rm)))
+        self._bufs[t] = (cp, ri, cm, rm)
+        return t
+
+    def poll(self, ticket: int, wait_ms: float = 0.0):
+        info = mcm_request_info()
+        rc = _check(lib().mcm_server_poll(self._h, int(ticket), ctypes.byref(info), float(wait_ms)))
+        if rc == 0:
+            return None
+        cp, ri, cm, rm = self._bufs.pop(ticket)
+        d = {f: getattr(info, f) for f, _ in mcm_request_info._fields_}
+        return d["card"], d, cm.numpy(), rm.numpy()
+
+    def stats(self) -> dict:
+        s = mcm_server_stats()
+        _check(lib().mcm_server_stats_get(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in mcm_server_stats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().mcm_server_destroy(self._h)
+            self._h = None
+            self._bufs.clear()
 
     def __del__(self):
         try:
