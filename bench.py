@@ -141,7 +141,7 @@ def bench_serving(pool_size, nreq, warmup, lam):
     r.update({"pool_graphs": pool_size, "pool_mean_n": round(sum(g.nc for g, _, _ in pool) / pool_size, 1),
               "pool_mean_nnz": round(sum(g.nnz for g, _, _ in pool) / pool_size, 1), "budget_bytes": 64 << 30,
               "peak_bytes": st["peak_bytes"], "launches_batched": st["launches_batched"],
-              "launches_whole_device": st["launches_grid"], "max_batch": st["max_batch_seen"],
+              "launches_multi_graph": st["launches_grid"], "max_batch": st["max_batch_seen"],
               "generate_s": round(t_gen, 2)})
     return r
 

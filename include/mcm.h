@@ -99,8 +99,12 @@ typedef struct {
  * mcm_match_batched -- maximum matchings of many independent graphs in one
  * device launch (one persistent kernel drains a work queue of graphs,
  * largest first; each graph is matched by one workgroup with the same
- * phases as mcm_match).  Defined to equal calling mcm_match on each graph:
- * the per-graph cardinalities are identical.
+ * phases as mcm_match).  Members with ncols + nrows above the option
+ * "multi_threshold" (default 2^15) are matched instead by a group of
+ * "multi_group" blocks each (default: a quarter of the CUs), several
+ * graphs per cooperative launch, after the workgroup kernel on the same
+ * stream.  Defined to equal calling mcm_match on each graph: the per-graph
+ * cardinalities are identical.
  *
  *   ngraphs            >= 0
  *   graphs             [ngraphs] HOST array of descriptors (copied)
@@ -123,7 +127,8 @@ int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs,
 /*
  * Batch plans: the descriptors of a fixed set of graphs are uploaded once
  * and the launch sequence of mcm_match_batched (control reset, the
- * one-workgroup-per-graph kernel, result copies) is captured in a hipGraph
+ * one-workgroup-per-graph kernel for every member, whatever its size,
+ * result copies) is captured in a hipGraph
  * that every mcm_batch_plan_run replays.  The arrays named at creation stay
  * bound to the plan: between runs the caller may change their contents
  * (new initial matchings, even new graphs of the same sizes) but not the
@@ -176,9 +181,9 @@ int64_t mcm_cheap_init(int32_t ncols, int32_t nrows, const int32_t *colptr, cons
  * the queue until memory returns.  A worker thread copies admitted inputs
  * to the device on a copy stream and keeps launching the batched matcher
  * over every admitted request whose inputs have arrived, while new requests
- * are admitted and copied; requests with nc + nr above a threshold
- * (max(wg_threshold, 2^17)) are matched by the whole device between
- * batches.  Every request starts from the device cheap matching and ends
+ * are admitted and copied; requests with nc + nr above 2^15 are matched
+ * by a group of blocks each (a quarter of the CUs), up to eight such
+ * requests per cooperative launch.  Every request starts from the device cheap matching and ends
  * with a maximum matching of its graph, copied back into the caller's
  * arrays; its memory is then released.
  *
@@ -288,7 +293,8 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *   "tuning"    path of an autotuner cache file (JSON lines) or ""
  *   "autotune"  "0" (default) | "1"            batch plans time candidates
  *   "block", "blocks_per_cu", "wg_block", "wg_threshold", "small_max",
- *   "batch_min", "split", "timeout_s"          launch-shape details (see
+ *   "batch_min", "split", "timeout_s", "max_blocks", "multi_threshold",
+ *   "multi_group"                              launch-shape details (see
  *                                              the host driver)
  * Return MCM_OK or MCM_EINVAL (unknown key or value).  mcm_get_option
  * writes the current value into buf (NUL-terminated, truncated to len).

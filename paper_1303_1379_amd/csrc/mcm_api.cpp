@@ -73,6 +73,8 @@ int64_t ensure_base(Workspace &w, int dev)
         w.info.clock_khz = rate;
     HIPCHK(hipMalloc(&w.ctrl, (size_t)L_NLINES * 128));
     HIPCHK(hipMalloc(&w.bar, (size_t)kMaxGridBlocks * 128));
+    HIPCHK(hipMalloc(&w.mctrl, (size_t)kMultiMax * L_NLINES * 128));
+    HIPCHK(hipMalloc(&w.mbar, (size_t)kMultiMax * kMaxGridBlocks * 128));
     HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&w.h_ctrl), (size_t)L_NLINES * 128, hipHostMallocDefault));
     HIPCHK(hipEventCreate(&w.ev0));
     HIPCHK(hipEventCreate(&w.ev1));
@@ -187,8 +189,9 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
         if (occ < 1) return fail(MCM_EHIP, "persistent kernel cannot be resident with block %d", o.block);
         int per_cu = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
         int blocks = w.info.ncu * per_cu;
-        HIPCHK(hipEventRecord(w.ev0, st));
+        if (o.max_blocks > 0 && blocks > o.max_blocks) blocks = o.max_blocks;
         if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
+        HIPCHK(hipEventRecord(w.ev0, st));
         HIPCHK(launch_persistent(g, w.ctrl, w.bar, ro, wave, blocks, o.block, st));
         HIPCHK(hipEventRecord(w.ev1, st));
         HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
@@ -308,7 +311,7 @@ int64_t run_single_wg(Workspace &w, const Options &o, int32_t nc, int32_t nr, co
 {
     int64_t rc;
     if ((rc = ensure_desc(w, 1))) return rc;
-    BatchDesc d;
+    BatchDesc d{};
     d.nc = nc;
     d.nr = nr;
     d.colptr = colptr;
@@ -409,6 +412,9 @@ int mcm_set_option(const char *key, const char *value)
     } else if (k == "blocks_per_cu") {
         if (!as_int(0, 32, &x)) return (int)fail(MCM_EINVAL, "blocks_per_cu must be in [0, 32]");
         g_opt.blocks_per_cu = (int)x;
+    } else if (k == "max_blocks") {
+        if (!as_int(0, kMaxGridBlocks, &x)) return (int)fail(MCM_EINVAL, "max_blocks must be in [0, 2048]");
+        g_opt.max_blocks = (int)x;
     } else if (k == "wg_block") {
         if (!as_int(64, 1024, &x) || x % 64) return (int)fail(MCM_EINVAL, "wg_block must be a multiple of 64 in [64, 1024]");
         g_opt.wg_block = (int)x;
@@ -422,6 +428,12 @@ int mcm_set_option(const char *key, const char *value)
         if (!as_int(0, (int64_t)1 << 30, &x) || (x != 0 && x < 64))
             return (int)fail(MCM_EINVAL, "split must be 0 or in [64, 2^30]");
         g_opt.split = (int)x;
+    } else if (k == "multi_threshold") {
+        if (!as_int(0, (int64_t)1 << 40, &x)) return (int)fail(MCM_EINVAL, "multi_threshold must be >= 0");
+        g_opt.multi_threshold = x;
+    } else if (k == "multi_group") {
+        if (!as_int(0, kMaxGridBlocks, &x)) return (int)fail(MCM_EINVAL, "multi_group must be in [0, 2048]");
+        g_opt.multi_group = (int)x;
     } else if (k == "small_max") {
         if (!as_int(0, (int64_t)1 << 30, &x)) return (int)fail(MCM_EINVAL, "small_max must be in [0, 2^30]");
         g_opt.small_max = x;
@@ -453,9 +465,12 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "autotune") v = o.autotune ? "1" : "0";
     else if (k == "block") v = std::to_string(o.block);
     else if (k == "blocks_per_cu") v = std::to_string(o.blocks_per_cu);
+    else if (k == "max_blocks") v = std::to_string(o.max_blocks);
     else if (k == "wg_block") v = std::to_string(o.wg_block);
     else if (k == "wg_threshold") v = std::to_string(o.wg_threshold);
     else if (k == "small_max") v = std::to_string(o.small_max);
+    else if (k == "multi_threshold") v = std::to_string(o.multi_threshold);
+    else if (k == "multi_group") v = std::to_string(o.multi_group);
     else if (k == "batch_min") v = std::to_string(o.batch_min);
     else if (k == "split") v = std::to_string(o.split);
     else if (k == "timeout_s") v = std::to_string(o.timeout_s);

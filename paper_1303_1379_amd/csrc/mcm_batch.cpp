@@ -135,7 +135,7 @@ void build_descs(int32_t ngraphs, const mcm_graph *graphs, const int32_t *cp, co
 {
     for (int32_t i = 0; i < ngraphs; ++i) {
         const mcm_graph &g = graphs[i];
-        BatchDesc d;
+        BatchDesc d{};
         d.nc = g.ncols;
         d.nr = g.nrows;
         d.colptr = cp ? cp + g.colptr_off : nullptr;
@@ -200,9 +200,21 @@ int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs, const int32_
     if ((rc = ensure_base(w, dev))) return rc;
     const size_t ce = (size_t)std::max<int64_t>(ex.col_ext, 1), re = (size_t)std::max<int64_t>(ex.row_ext, 1);
     if ((rc = ensure_graph(w, ce, re, ce))) return rc;  // queues: 2 * col_ext entries in all
-    if ((rc = ensure_desc(w, (size_t)ngraphs))) return rc;
+    if ((rc = ensure_desc(w, 2 * (size_t)ngraphs))) return rc;  // second half: large members, packed
     build_descs(ngraphs, graphs, colptr_all, rowind_all, init_cmatch_all, init_rmatch_all, out_cmatch_all,
                 out_rmatch_all, w.rw, w.pred, w.cdone, w.fq, w.ends, w.h_desc, w.h_order);
+    // Members above multi_threshold vertices are matched by groups of blocks,
+    // several graphs per cooperative launch; the order is largest first, so
+    // they are its prefix.
+    int32_t nlarge = 0;
+    if (o.multi_threshold > 0)
+        while (nlarge < ngraphs) {
+            const mcm_graph &g = graphs[w.h_order[nlarge]];
+            if ((int64_t)g.ncols + g.nrows <= o.multi_threshold) break;
+            w.h_desc[ngraphs + nlarge] = w.h_desc[w.h_order[nlarge]];
+            ++nlarge;
+        }
+    const int32_t nsmall = ngraphs - nlarge;
     BatchCfg cfg = default_cfg(o);
     if (o.mapping == 2) tune_lookup(o.tuning, tune_key(w.info.arch, ngraphs, ex.verts), &cfg);
     uint32_t flags = base_flags(o, 0, 0);
@@ -212,18 +224,40 @@ int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs, const int32_
     ro.split = 0;  // per-graph queue slices hold exactly nc entries
     ro.batch_min = (uint32_t)cfg.batch_min;
     HIPCHK(prepare_match_wg(cfg.block));
-    const int blocks = batch_blocks(w.info, cfg.wave, cfg.block, ngraphs);
-    HIPCHK(hipMemcpyAsync(w.desc, w.h_desc, sizeof(BatchDesc) * ngraphs, hipMemcpyHostToDevice, st));
+    const int blocks = batch_blocks(w.info, cfg.wave, cfg.block, std::max(nsmall, 1));
+    // multi-graph launch shape: `group` blocks per graph, `per_launch` graphs
+    // co-resident (a cooperative launch must fit the device at once)
+    const bool mwave = (flags & F_WAVE) != 0;
+    int group = 1, per_launch = 1;
+    if (nlarge) {
+        int occ = 0;
+        HIPCHK(multi_occupancy(mwave, o.block, &occ));
+        const int resident = w.info.ncu * std::max(occ, 0);
+        if (resident < 1) return fail(MCM_EHIP, "multi-graph kernel does not fit a CU with block %d", o.block);
+        group = o.multi_group > 0 ? o.multi_group : std::max(1, w.info.ncu / 4);
+        group = std::min(group, std::min(resident, kMaxGridBlocks));
+        per_launch = std::max(1, std::min(kMultiMax, resident / group));
+    }
+    RunOpt mro = run_opt(o, flags, std::max<int64_t>(ex.col_ext, 1), w.info);
+    mro.split = 0;  // same queue slices as above
+    HIPCHK(hipMemcpyAsync(w.desc, w.h_desc, sizeof(BatchDesc) * (ngraphs + nlarge), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(w.order, w.h_order, sizeof(int32_t) * ngraphs, hipMemcpyHostToDevice, st));
     HIPCHK(launch_zero_ctrl(w.ctrl, st));
     HIPCHK(hipEventRecord(w.ev0, st));
-    HIPCHK(launch_match_wg(w.desc, w.order, ngraphs, w.card, w.ctrl, ro, cfg.wave, blocks, cfg.block, st));
+    if (nsmall)
+        HIPCHK(launch_match_wg(w.desc, w.order + nlarge, nsmall, w.card, w.ctrl, ro, cfg.wave, blocks, cfg.block, st));
+    for (int32_t j = 0; j < nlarge; j += per_launch) {
+        const int32_t n = std::min(per_launch, nlarge - j);
+        HIPCHK(launch_multi(w.desc + ngraphs + j, n, group, w.mctrl, w.mbar, w.card + ngraphs + j, mro, mwave, o.block,
+                            st));
+    }
     HIPCHK(hipEventRecord(w.ev1, st));
-    HIPCHK(hipMemcpyAsync(w.h_card, w.card, sizeof(int64_t) * ngraphs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(w.h_card, w.card, sizeof(int64_t) * (ngraphs + nlarge), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, w.ev0, w.ev1));
+    for (int32_t j = 0; j < nlarge; ++j) w.h_card[w.h_order[j]] = w.h_card[ngraphs + j];
     int64_t total = 0;
     bool bad = false;
     for (int32_t i = 0; i < ngraphs; ++i) {

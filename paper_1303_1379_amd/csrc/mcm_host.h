@@ -33,6 +33,10 @@ hipError_t launch_match_wg(const BatchDesc *descs, const int32_t *order, int32_t
 hipError_t prepare_match_wg(int block);
 hipError_t match_wg_occupancy(bool wave, int block, int *per_cu);
 hipError_t launch_cheap_init(const BatchDesc *descs, int32_t ngraphs, hipStream_t st);
+hipError_t multi_occupancy(bool wave, int block, int *per_cu);
+constexpr int kMultiMax = 8;  // graphs per multi-graph launch (upper bound)
+hipError_t launch_multi(const BatchDesc *descs, int32_t ngraphs, int group, uint32_t *ctrls, uint32_t *bars,
+                        int64_t *card, const RunOpt &o, bool wave, int block, hipStream_t st);
 
 namespace host {
 
@@ -60,11 +64,14 @@ struct Options {
     bool autotune = false;    // batch plans time the candidate configurations
     int block = 1024;         // persistent block size
     int blocks_per_cu = 1;    // 0 = occupancy limit
+    int max_blocks = 0;       // cap on persistent blocks (0 = one set per CU)
     int wg_block = 1024;      // one-workgroup matcher block size
     int64_t wg_threshold = 16384;  // nc + nr at or below which one workgroup matches alone
     int64_t small_max = 256;  // frontiers up to this size are expanded by one workgroup
     int batch_min = 8;        // fewest frontier entries per wavefront batch
     int split = 64;           // heavier columns enter the frontier in pieces of this many edges (0 = off)
+    int64_t multi_threshold = 1 << 15;  // batch members with nc + nr above this: multi-graph launches (0 = never)
+    int multi_group = 0;      // blocks per graph in a multi-graph launch (0 = CUs / 4)
     double timeout_s = 20.0;  // device barrier wait limit
 };
 Options opts();
@@ -89,6 +96,8 @@ struct Workspace {
     uint32_t *bar = nullptr;     // grid barrier arrival flags
     BatchDesc *desc = nullptr;
     size_t cap_desc = 0;
+    uint32_t *mctrl = nullptr;   // control blocks of a multi-graph launch
+    uint32_t *mbar = nullptr;    // its arrival lines
     int32_t *order = nullptr;
     int64_t *card = nullptr;
     uint32_t *h_ctrl = nullptr;  // pinned

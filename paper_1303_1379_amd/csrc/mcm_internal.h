@@ -82,6 +82,7 @@ struct BatchDesc {
     uint32_t *cdone;
     int4 *fq;
     int32_t *ends;
+    int64_t qcap;                     // entries per frontier queue (fq, fq + qcap); 0 = nc
 };
 
 // Per-wavefront LDS staging of queue pushes.

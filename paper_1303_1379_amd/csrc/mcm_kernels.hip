@@ -234,7 +234,7 @@ DEV void add_stat(uint64_t *stats, int idx, uint64_t v)
 struct Acc {
     uint64_t edges = 0, expanded = 0, claimed = 0, found = 0, alt = 0, fix = 0, roots = 0;
     uint64_t t_expand = 0, t_flush = 0, t_barrier = 0, t_small = 0, t_augment = 0;
-    DEV void flush(uint64_t *stats)
+    DEV void flush(uint64_t *stats, bool leader)
     {
         add_stat(stats, S_EDGES, edges);
         add_stat(stats, S_EXPANDED, expanded);
@@ -243,7 +243,7 @@ struct Acc {
         add_stat(stats, S_ALT, alt);
         add_stat(stats, S_FIX, fix);
         add_stat(stats, S_ROOTS, roots);
-        if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (leader) {
             stats[S_T_EXPAND * 16] += t_expand;
             stats[S_T_FLUSH * 16] += t_flush;
             stats[S_T_BARRIER * 16] += t_barrier;
@@ -433,19 +433,25 @@ DEV void fix_matching(const DevGraph &g, uint32_t tid, uint32_t nthreads, uint32
 // of block 0 polls all flags, then releases the epoch.  Agent-scope release
 // before arriving, acquire after leaving; every wait is bounded.  Returns
 // false (in all blocks, eventually) once any block set a status.
-DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t timeout, int *s_ok)
+// The blocks that synchronise: block `b` of a group of `n` (the whole grid,
+// or one graph's share of a multi-graph launch).
+struct Grp {
+    uint32_t b, n;
+};
+
+DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t timeout, int *s_ok, Grp gr)
 {
     __syncthreads();
     ++epoch;
     uint32_t *gen = line(ctrl, L_BAR_GEN);
-    if (blockIdx.x == 0) {
+    if (gr.b == 0) {
         if (threadIdx.x < 64) {
             int ok = status_of(ctrl) == 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const uint64_t t0 = wall_clock64();
             while (ok) {
                 bool mine = true;
-                for (uint32_t b = 1 + threadIdx.x; b < gridDim.x; b += 64)
+                for (uint32_t b = 1 + threadIdx.x; b < gr.n; b += 64)
                     mine &= ld_u<kAgent>(bar + (size_t)b * kLineWords) == epoch;
                 if (__ballot(!mine) == 0) break;
                 if (status_of(ctrl) != 0) ok = 0;
@@ -462,7 +468,7 @@ DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t t
         int ok = status_of(ctrl) == 0;
         if (ok) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(bar + (size_t)blockIdx.x * kLineWords, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(bar + (size_t)gr.b * kLineWords, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint64_t t0 = wall_clock64();
             while (ld_u<kAgent>(gen) != epoch) {
                 if (status_of(ctrl) != 0) { ok = 0; break; }
@@ -535,13 +541,13 @@ DEV uint32_t small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, ui
 // The phase loop of Algorithm 1 over the whole grid (cooperative launch).
 template <bool WAVE>
 DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt &o, uint64_t *stats, Stage &st,
-                  uint32_t *s_tmp, uint32_t *s_loc, int *s_ok, uint32_t *ph_out, uint32_t *lv_out)
+                  uint32_t *s_tmp, uint32_t *s_loc, int *s_ok, uint32_t *ph_out, uint32_t *lv_out, Grp gr)
 {
     const uint32_t flags = o.flags;
-    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nthreads = gridDim.x * blockDim.x;
-    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    const uint32_t wave = gr.b * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gr.n * (blockDim.x >> 6);
+    const uint32_t tid = gr.b * blockDim.x + threadIdx.x, nthreads = gr.n * blockDim.x;
+    const bool leader = gr.b == 0 && threadIdx.x == 0;
     const bool timing = (flags & F_STATS) != 0;
     Acc acc;
     uint32_t epoch = 0, total_levels = 0, ph = 1;
@@ -550,7 +556,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     // grid barrier, with the time block 0 spends in it counted (stats=1)
     auto sync = [&]() -> bool {
         const uint64_t t0 = timing ? wall_clock64() : 0;
-        const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok);
+        const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr);
         if (timing) acc.t_barrier += wall_clock64() - t0;
         return ok;
     };
@@ -564,7 +570,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             if (n == 0) break;
             if ((uint32_t)L > o.max_levels) { if (leader) set_status(ctrl, kEInternal); return false; }
             if (n <= o.small_max) {
-                if (blockIdx.x == 0) {
+                if (gr.b == 0) {
                     const uint64_t t0 = timing ? wall_clock64() : 0;
                     total_levels += small_levels<WAVE>(g, ctrl, o, ph, L, n, st, s_tmp, s_loc, acc);
                     if (timing) acc.t_small += wall_clock64() - t0;
@@ -597,7 +603,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         if (timing) acc.t_augment += wall_clock64() - ta;
     }
     if (leader) { *ph_out = ph; *lv_out = total_levels; }
-    if (timing) acc.flush(stats);
+    if (timing) acc.flush(stats, leader);
     return true;
 }
 
@@ -640,7 +646,7 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint64_t 
     __syncthreads();
     if (flags & F_STATS) {
         acc.t_expand = acc.t_flush = 0;  // per-graph timings are not meaningful summed over blocks
-        acc.flush(stats);
+        acc.flush(stats, false);
     }
     *ph_out = ph;
     *lv_out = total_levels;
@@ -709,10 +715,101 @@ __global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl,
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
     uint32_t ph = 0, lv = 0;
-    if (run_grid<WAVE>(g, ctrl, bar, o, stats, st, s_tmp, s_loc, &s_ok, &ph, &lv) && blockIdx.x == 0 &&
+    if (run_grid<WAVE>(g, ctrl, bar, o, stats, st, s_tmp, s_loc, &s_ok, &ph, &lv, Grp{blockIdx.x, gridDim.x}) &&
+        blockIdx.x == 0 && threadIdx.x == 0) {
+        *line(ctrl, L_PHASE) = ph;
+        *line(ctrl, L_LEVELS) = lv;
+    }
+}
+
+// ---------------------------------------------------------------------
+// Several large graphs in one cooperative launch: graph i of the launch is
+// matched by blocks [i*group, (i+1)*group) with the same phase loop as
+// k_persistent, synchronised by a barrier of its own group (own control
+// block and arrival lines).  One launch keeps all groups co-resident.
+// State setup and the final unpack are separate launches before and after.
+DEV DevGraph graph_of(const BatchDesc &d)
+{
+    DevGraph g;
+    g.colptr = d.colptr;
+    g.rowind = d.rowind;
+    g.nc = d.nc;
+    g.nr = d.nr;
+    g.cmatch = d.out_c;
+    g.rw = d.rw;
+    g.pred = d.pred;
+    g.cdone = d.cdone;
+    g.fq0 = d.fq;
+    g.fq1 = d.fq + (d.qcap ? d.qcap : d.nc);
+    g.ends = d.ends;
+    g.clevel = nullptr;
+    return g;
+}
+
+// blockIdx.y = graph: working state from the initial matching, |M| slot and
+// the graph's control block and arrival lines reset.
+__global__ void k_setup_multi(const BatchDesc *descs, int32_t ngraphs, uint32_t *ctrls, uint32_t *bars,
+                              uint32_t bar_lines, int64_t *card)
+{
+    for (int32_t gi = blockIdx.y; gi < ngraphs; gi += gridDim.y) {
+        const BatchDesc d = descs[gi];
+        const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+        for (uint32_t c = tid; c < (uint32_t)d.nc; c += nt) {
+            d.out_c[c] = d.init_c ? d.init_c[c] : -1;
+            d.cdone[c] = 0;
+        }
+        for (uint32_t r = tid; r < (uint32_t)d.nr; r += nt) d.rw[r] = (uint64_t)(uint32_t)(d.init_r ? d.init_r[r] : -1);
+        uint32_t *ctrl = ctrls + (size_t)gi * L_NLINES * kLineWords;
+        uint32_t *bar = bars + (size_t)gi * bar_lines * kLineWords;
+        for (uint32_t i = tid; i < (uint32_t)(L_NLINES * kLineWords); i += nt) ctrl[i] = 0;
+        for (uint32_t i = tid; i < bar_lines * (uint32_t)kLineWords; i += nt) bar[i] = 0;
+        if (tid == 0) card[gi] = 0;
+    }
+}
+
+template <bool WAVE>
+__global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *descs, int32_t ngraphs, uint32_t group,
+                                                           uint32_t *ctrls, uint32_t *bars, RunOpt o)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int s_ok;
+    __shared__ uint32_t s_loc[8];
+    const uint32_t gi = blockIdx.x / group;
+    if (gi >= (uint32_t)ngraphs) return;  // whole block: never part of any barrier
+    const Grp gr{blockIdx.x % group, group};
+    const BatchDesc d = descs[gi];
+    if (d.nc == 0 || d.nr == 0) return;   // whole group
+    DevGraph g = graph_of(d);
+    uint32_t *ctrl = ctrls + (size_t)gi * L_NLINES * kLineWords;
+    uint32_t *bar = bars + (size_t)gi * group * kLineWords;
+    Stage st = make_stage(smem);
+    uint32_t *s_tmp = stage_tmp(smem);
+    uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
+    uint32_t ph = 0, lv = 0;
+    if (run_grid<WAVE>(g, ctrl, bar, o, stats, st, s_tmp, s_loc, &s_ok, &ph, &lv, gr) && gr.b == 0 &&
         threadIdx.x == 0) {
         *line(ctrl, L_PHASE) = ph;
         *line(ctrl, L_LEVELS) = lv;
+    }
+}
+
+// blockIdx.y = graph: unpack rmatch, |M| = #{c : cmatch[c] >= 0} into
+// card[graph]; a graph whose group hit a watchdog gets the status instead.
+__global__ void k_finish_multi(const BatchDesc *descs, int32_t ngraphs, uint32_t *ctrls, int64_t *card)
+{
+    for (int32_t gi = blockIdx.y; gi < ngraphs; gi += gridDim.y) {
+        const BatchDesc d = descs[gi];
+        const int32_t status = *(const int32_t *)line(ctrls + (size_t)gi * L_NLINES * kLineWords, L_STATUS);
+        const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+        if (status != 0) {
+            if (tid == 0) card[gi] = status;
+            continue;
+        }
+        for (uint32_t r = tid; r < (uint32_t)d.nr; r += nt) d.out_r[r] = (int32_t)(uint32_t)d.rw[r];
+        uint64_t m = 0;
+        for (uint32_t c = tid; c < (uint32_t)d.nc; c += nt) m += (d.out_c[c] >= 0);
+        m = wave_sum(m);
+        if (__lane_id() == 0 && m) atomicAdd((unsigned long long *)&card[gi], (unsigned long long)m);
     }
 }
 
@@ -725,7 +822,7 @@ __global__ void k_init_roots(DevGraph g, uint32_t *ctrl, RunOpt o)
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nwaves = gridDim.x * (blockDim.x >> 6);
     Acc acc;
     init_roots(g, wave, nwaves, o, line(ctrl, L_FCOUNT0), st, stage_tmp(smem), acc);
-    if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0))); }
+    if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false); }
 }
 
 template <bool WAVE>
@@ -744,7 +841,7 @@ __global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint
                line(ctrl, L_FOUND0 + L % 3)};
     Acc acc;
     expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
-    if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0))); }
+    if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false); }
 }
 
 __global__ void k_alternate(DevGraph g, uint32_t *ctrl, uint32_t flags)
@@ -752,14 +849,14 @@ __global__ void k_alternate(DevGraph g, uint32_t *ctrl, uint32_t flags)
     const uint32_t ne = *line(ctrl, L_NENDS);
     Acc acc;
     alternate<kAgent>(g, ne, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, flags, ctrl, acc);
-    if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)));
+    if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
 }
 
 __global__ void k_fix(DevGraph g, uint32_t *ctrl, uint32_t flags)
 {
     Acc acc;
     fix_matching(g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, flags, acc);
-    if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)));
+    if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int i = 0; i < 3; ++i) { *line(ctrl, L_FCOUNT0 + i) = 0; *line(ctrl, L_FOUND0 + i) = 0; }
         *line(ctrl, L_NENDS) = 0;
@@ -1062,6 +1159,44 @@ hipError_t launch_cheap_init(const BatchDesc *descs, int32_t ngraphs, hipStream_
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cheap_init, grid, dim3(256), 0, st, descs, ngraphs);
+    return hipGetLastError();
+}
+
+static const void *multi_fn(bool wave)
+{
+    return wave ? reinterpret_cast<const void *>(&k_persistent_multi<true>)
+                : reinterpret_cast<const void *>(&k_persistent_multi<false>);
+}
+
+// Blocks per CU of the multi-graph persistent kernel at this block size.
+hipError_t multi_occupancy(bool wave, int block, int *per_cu)
+{
+    const int lds = stage_lds_bytes(block / 64);
+    hipError_t e = allow_lds(multi_fn(wave), lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, multi_fn(wave), block, lds);
+}
+
+// setup -> cooperative multi-graph launch (ngraphs groups of `group` blocks)
+// -> finish; card[ngraphs] receives |M_g|.  ctrls: ngraphs control blocks,
+// bars: ngraphs * group arrival lines.
+hipError_t launch_multi(const BatchDesc *descs, int32_t ngraphs, int group, uint32_t *ctrls, uint32_t *bars,
+                        int64_t *card, const RunOpt &o, bool wave, int block, hipStream_t st)
+{
+    const dim3 g2(256, (unsigned)(ngraphs < 65535 ? ngraphs : 65535));
+    hipLaunchKernelGGL(k_setup_multi, g2, dim3(256), 0, st, descs, ngraphs, ctrls, bars, (uint32_t)group, card);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const BatchDesc *dd = descs;
+    int32_t ng = ngraphs;
+    uint32_t gp = (uint32_t)group;
+    uint32_t *cc = ctrls, *bb = bars;
+    RunOpt oo = o;
+    void *args[] = {&dd, &ng, &gp, &cc, &bb, &oo};
+    e = hipLaunchCooperativeKernel(multi_fn(wave), dim3((unsigned)(ngraphs * group)), dim3(block), args,
+                                   (unsigned)stage_lds_bytes(block / 64), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finish_multi, g2, dim3(256), 0, st, descs, ngraphs, ctrls, card);
     return hipGetLastError();
 }
 

@@ -6,8 +6,11 @@
 // compute stream busy: every launch takes all admitted requests whose
 // inputs have arrived (one workgroup per graph, the batched kernel), while
 // newly arriving requests are admitted, copied and queued for the next
-// launch.  Requests larger than a threshold get the whole device (the
-// persistent single-graph kernel) between batched launches.  Results are
+// launch.  Requests larger than a threshold are matched several at a time
+// by one cooperative launch of the persistent kernel in which each request
+// has its own group of blocks (k_persistent_multi); launches of both kinds
+// follow each other on one compute stream, so at most one cooperative
+// launch is ever in flight.  Results are
 // copied back on the copy stream; a request's memory returns to the budget
 // when its results are on the host.  Every request starts from the device
 // cheap matching (mcm_cheap_init) and is matched to maximum exactly as
@@ -109,52 +112,19 @@ struct Request {
     int4 *fq = nullptr;
     size_t qcap = 0;
     bool big = false;
-    BatchDesc *d_desc = nullptr;   // one-entry descriptor in the request's device memory
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    // pinned 128-byte slot: [0] |M| (whole-device path), [1] status, [2..] staged descriptor
-    int64_t *pin = nullptr;
     bool card_known = false;
     mcm_request_info info{};
 };
 
-// Pinned host slots of 128 bytes, allocated in chunks and recycled.
-class PinnedSlots {
-  public:
-    int64_t *get()
-    {
-        if (free_.empty()) {
-            char *chunk = nullptr;
-            if (hipHostMalloc(reinterpret_cast<void **>(&chunk), 128 * 1024, hipHostMallocDefault) != hipSuccess)
-                return nullptr;
-            chunks_.push_back(chunk);
-            for (int i = 0; i < 1024; ++i) free_.push_back(reinterpret_cast<int64_t *>(chunk + 128 * i));
-        }
-        int64_t *p = free_.back();
-        free_.pop_back();
-        return p;
-    }
-    void put(int64_t *p)
-    {
-        if (p) free_.push_back(p);
-    }
-    void release()
-    {
-        for (char *c : chunks_) (void)hipHostFree(c);
-        chunks_.clear();
-        free_.clear();
-    }
-
-  private:
-    std::vector<char *> chunks_;
-    std::vector<int64_t *> free_;
-};
-
-struct Slot {  // one in-flight batched launch
+struct Slot {  // one in-flight launch: batched (one workgroup per graph) or multi-graph persistent
     BatchDesc *d_desc = nullptr, *h_desc = nullptr;
     int64_t *d_card = nullptr, *h_card = nullptr;
-    uint32_t *d_ctrl = nullptr, *h_ctrl = nullptr;
+    uint32_t *d_ctrl = nullptr, *h_ctrl = nullptr;   // kMultiMax control blocks
+    uint32_t *d_bar = nullptr;                        // arrival lines of the multi-graph launch
     hipEvent_t done = nullptr;
     bool busy = false;
+    int ngroups = 0;                                  // > 0: a multi-graph launch
     std::vector<Request *> reqs;
 };
 
@@ -165,17 +135,18 @@ struct mcm_server {
     DevInfo info;
     Options opt;
     int32_t max_batch = 1024;
-    int64_t big_threshold = 1 << 17;  // nc + nr above which a request gets the whole device
+    int64_t big_threshold = 1 << 15;  // nc + nr above which a request joins a multi-graph launch
+    int group = 64;                   // blocks per large request in a multi-graph launch
+    int multi_max = 4;                // large requests per multi-graph launch
+    std::deque<Request *> big_ready;  // large requests waiting for a launch
     Arena arena;
     hipStream_t compute = nullptr, copy = nullptr;
     std::vector<Slot> slots;
-    uint32_t *g_ctrl = nullptr, *g_bar = nullptr;  // whole-device path
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Request *> pending;            // waiting for memory, in arrival order
     std::vector<Request *> copying, running;  // inputs on their way; launched
     std::unordered_map<int64_t, Request *> live;  // every request not yet polled as done
-    PinnedSlots pins;
     int64_t next_ticket = 1;
     std::atomic<bool> stop{false};
     std::thread worker;
@@ -197,8 +168,7 @@ size_t req_bytes(const mcm_server *s, int32_t nc, int32_t nr, int64_t nnz, bool 
     const size_t q = big ? *qcap : (size_t)nc;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     return al(4 * ((size_t)nc + 1)) + al(4 * (size_t)nnz) + al(4 * (size_t)nc) + al(4 * (size_t)nr) +
-           al(8 * (size_t)nr) + al(4 * (size_t)nr) + al(4 * (size_t)nr) + al(4 * (size_t)nc) + al(32 * q) +
-           al(sizeof(BatchDesc));
+           al(8 * (size_t)nr) + al(4 * (size_t)nr) + al(4 * (size_t)nr) + al(4 * (size_t)nc) + al(32 * q);
 }
 
 void carve(mcm_server *s, Request *r)
@@ -214,12 +184,11 @@ void carve(mcm_server *s, Request *r)
     r->ends = reinterpret_cast<int32_t *>(take(4 * (size_t)r->nr));
     r->cdone = reinterpret_cast<uint32_t *>(take(4 * (size_t)r->nc));
     r->fq = reinterpret_cast<int4 *>(take(32 * (r->big ? r->qcap : (size_t)r->nc)));
-    r->d_desc = reinterpret_cast<BatchDesc *>(take(sizeof(BatchDesc)));
 }
 
 BatchDesc desc_of(const Request *r)
 {
-    BatchDesc d;
+    BatchDesc d{};
     d.nc = r->nc;
     d.nr = r->nr;
     d.colptr = r->colptr;
@@ -233,6 +202,7 @@ BatchDesc desc_of(const Request *r)
     d.cdone = r->cdone;
     d.fq = r->fq;
     d.ends = r->ends;
+    d.qcap = r->big ? (int64_t)r->qcap : 0;
     return d;
 }
 
@@ -303,54 +273,44 @@ int64_t launch_batch(mcm_server *s, Slot &slot, std::vector<Request *> &reqs)
         if ((rc = start_copy_back(s, r, slot.done))) return rc;
     }
     slot.busy = true;
+    slot.ngroups = 0;
     slot.reqs = reqs;
     s->st.launches_batched += 1;
     s->st.max_batch_seen = std::max<int64_t>(s->st.max_batch_seen, n);
     return 0;
 }
 
-int64_t launch_big(mcm_server *s, Request *r)
+// Up to multi_max large requests in one cooperative launch, `group` blocks each.
+int64_t launch_multi_reqs(mcm_server *s, Slot &slot, std::vector<Request *> &reqs)
 {
-    // the same steps as mcm_match, on the request's own workspace
-    DevGraph g;
-    g.colptr = r->colptr;
-    g.rowind = r->nnz ? r->rowind : nullptr;
-    g.nc = r->nc;
-    g.nr = r->nr;
-    g.cmatch = r->cmatch;
-    g.rw = r->rw;
-    g.pred = r->pred;
-    g.cdone = r->cdone;
-    g.fq0 = r->fq;
-    g.fq1 = r->fq + r->qcap;
-    g.ends = r->ends;
-    g.clevel = nullptr;
-    BatchDesc *staged = reinterpret_cast<BatchDesc *>(r->pin + 2);
-    *staged = desc_of(r);
-    HIPCHK(hipMemcpyAsync(r->d_desc, staged, sizeof(BatchDesc), hipMemcpyHostToDevice, s->compute));
-    HIPCHK(launch_cheap_init(r->d_desc, 1, s->compute));
+    const int32_t n = (int32_t)reqs.size();
+    for (int32_t i = 0; i < n; ++i) slot.h_desc[i] = desc_of(reqs[i]);
+    HIPCHK(hipMemcpyAsync(slot.d_desc, slot.h_desc, sizeof(BatchDesc) * n, hipMemcpyHostToDevice, s->compute));
+    HIPCHK(launch_cheap_init(slot.d_desc, n, s->compute));
     const uint32_t flags = base_flags(s->opt, 0, 0) & ~(uint32_t)F_STATS;
-    const RunOpt ro = run_opt(s->opt, flags, r->nc, s->info);
-    HIPCHK(launch_setup(g, r->cmatch, r->rmatch, s->g_ctrl, s->g_bar, flags, s->compute));
-    int occ = 0;
-    HIPCHK(persistent_occupancy((flags & F_WAVE) != 0, s->opt.block, &occ));
-    occ = std::max(occ, 1);
-    const int per_cu = s->opt.blocks_per_cu > 0 ? std::min(s->opt.blocks_per_cu, occ) : occ;
-    const int blocks = std::min(s->info.ncu * per_cu, kMaxGridBlocks);
-    HIPCHK(launch_persistent(g, s->g_ctrl, s->g_bar, ro, (flags & F_WAVE) != 0, blocks, s->opt.block, s->compute));
-    HIPCHK(launch_finish(g, r->rmatch, s->g_ctrl, s->compute));
-    // |M| and the watchdog status into the request's own pinned slot
-    HIPCHK(hipMemcpyAsync(&r->pin[0], ctrl_line(s->g_ctrl, L_CARD), sizeof(int64_t), hipMemcpyDeviceToHost, s->compute));
-    HIPCHK(hipMemcpyAsync(&r->pin[1], ctrl_line(s->g_ctrl, L_STATUS), sizeof(int32_t), hipMemcpyDeviceToHost, s->compute));
-    HIPCHK(hipEventRecord(r->ev_in, s->compute));  // ev_in is free again: reuse it as "launch done"
-    r->state = Q_RUNNING;
-    r->info.start_ms = s->now_ms();
-    r->info.path = 1;
-    r->info.batch_size = 1;
-    r->card_known = false;
-    s->running.push_back(r);
+    const RunOpt ro = run_opt(s->opt, flags, 1 << 30, s->info);
+    HIPCHK(launch_multi(slot.d_desc, n, s->group, slot.d_ctrl, slot.d_bar, slot.d_card, ro, (flags & F_WAVE) != 0,
+                        s->opt.block, s->compute));
+    HIPCHK(hipMemcpyAsync(slot.h_card, slot.d_card, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s->compute));
+    HIPCHK(hipMemcpyAsync(slot.h_ctrl, slot.d_ctrl, (size_t)n * L_NLINES * 128, hipMemcpyDeviceToHost, s->compute));
+    HIPCHK(hipEventRecord(slot.done, s->compute));
+    const double t = s->now_ms();
+    for (int32_t i = 0; i < n; ++i) {
+        Request *r = reqs[i];
+        r->state = Q_RUNNING;
+        r->info.start_ms = t;
+        r->info.path = 1;
+        r->info.batch_size = n;
+        r->card_known = false;
+        s->running.push_back(r);
+        int64_t rc;
+        if ((rc = start_copy_back(s, r, slot.done))) return rc;
+    }
+    slot.busy = true;
+    slot.ngroups = n;
+    slot.reqs = reqs;
     s->st.launches_grid += 1;
-    return start_copy_back(s, r, r->ev_in);
+    return 0;
 }
 
 void complete(mcm_server *s, Request *r)
@@ -400,15 +360,27 @@ void worker_loop(mcm_server *s)
             progressed = true;
         }
         for (Request *r : small) s->copying.push_back(r);  // retried next round (event already complete)
-        for (Request *r : big) {
-            if (s->status) break;
-            if (launch_big(s, r)) s->status = MCM_EHIP;
+        // large requests: up to multi_max per cooperative launch, one launch per free slot
+        for (Request *r : big) s->big_ready.push_back(r);
+        while (!s->big_ready.empty() && !s->status) {
+            Slot *free_slot = nullptr;
+            for (auto &sl : s->slots)
+                if (!sl.busy) { free_slot = &sl; break; }
+            if (!free_slot) break;
+            std::vector<Request *> take;
+            while (!s->big_ready.empty() && (int)take.size() < s->multi_max) {
+                take.push_back(s->big_ready.front());
+                s->big_ready.pop_front();
+            }
+            if (launch_multi_reqs(s, *free_slot, take)) s->status = MCM_EHIP;
             progressed = true;
         }
         // finished batched launches: their cards become known
         for (auto &sl : s->slots) {
             if (sl.busy && hipEventQuery(sl.done) == hipSuccess) {
-                if (*ctrl_line(sl.h_ctrl, L_STATUS) != 0) s->status = MCM_EINTERNAL;
+                for (int k = 0; k < std::max(sl.ngroups, 1); ++k)
+                    if (*ctrl_line(sl.h_ctrl + (size_t)k * L_NLINES * kLineWords, L_STATUS) != 0)
+                        s->status = MCM_EINTERNAL;
                 for (size_t i = 0; i < sl.reqs.size(); ++i) {
                     sl.reqs[i]->info.card = sl.h_card[i];
                     sl.reqs[i]->card_known = true;
@@ -421,11 +393,6 @@ void worker_loop(mcm_server *s)
         // results on the host
         for (size_t i = 0; i < s->running.size();) {
             Request *r = s->running[i];
-            if (!r->card_known && r->info.path == 1 && hipEventQuery(r->ev_in) == hipSuccess) {
-                if ((int32_t)r->pin[1] != 0) s->status = MCM_EINTERNAL;
-                r->info.card = r->pin[0];
-                r->card_known = true;
-            }
             if (r->card_known && hipEventQuery(r->ev_out) == hipSuccess) {
                 complete(s, r);
                 s->running[i] = s->running.back();
@@ -464,25 +431,33 @@ int64_t mcm_server_create(int64_t hbm_budget_bytes, int32_t max_batch, mcm_serve
     }
     s->opt = opts();
     s->max_batch = max_batch;
-    s->big_threshold = std::max<int64_t>(s->opt.wg_threshold, 1 << 17);
+    s->big_threshold = std::max<int64_t>(s->opt.wg_threshold, 1 << 15);
     if (s->arena.init((size_t)hbm_budget_bytes)) return bail(MCM_ENOMEM);
     if (hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(MCM_EHIP, "stream creation failed"));
+    // large requests: `group` blocks each (one persistent block per CU), as many per launch as the
+    // device holds at once
+    s->group = std::max(1, s->info.ncu / 4);
+    {
+        int occ = 0;
+        if (multi_occupancy((base_flags(s->opt, 0, 0) & F_WAVE) != 0, s->opt.block, &occ) != hipSuccess || occ < 1)
+            return bail(fail(MCM_EHIP, "multi-graph kernel cannot be resident with block %d", s->opt.block));
+        s->multi_max = std::max(1, std::min(kMultiMax, s->info.ncu * occ / s->group));
+    }
+    const int ndesc = std::max(max_batch, kMultiMax);
     s->slots.resize(2);
     for (auto &sl : s->slots) {
-        if (hipMalloc(&sl.d_desc, sizeof(BatchDesc) * max_batch) != hipSuccess ||
-            hipMalloc(&sl.d_card, sizeof(int64_t) * max_batch) != hipSuccess ||
-            hipMalloc(&sl.d_ctrl, (size_t)L_NLINES * 128) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&sl.h_desc), sizeof(BatchDesc) * max_batch, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&sl.h_card), sizeof(int64_t) * max_batch, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&sl.h_ctrl), (size_t)L_NLINES * 128, hipHostMallocDefault) != hipSuccess ||
+        if (hipMalloc(&sl.d_desc, sizeof(BatchDesc) * ndesc) != hipSuccess ||
+            hipMalloc(&sl.d_card, sizeof(int64_t) * ndesc) != hipSuccess ||
+            hipMalloc(&sl.d_ctrl, (size_t)kMultiMax * L_NLINES * 128) != hipSuccess ||
+            hipMalloc(&sl.d_bar, (size_t)kMultiMax * s->group * 128) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&sl.h_desc), sizeof(BatchDesc) * ndesc, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&sl.h_card), sizeof(int64_t) * ndesc, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&sl.h_ctrl), (size_t)kMultiMax * L_NLINES * 128, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
             return bail(fail(MCM_ENOMEM, "server slot allocation failed"));
     }
-    if (hipMalloc(&s->g_ctrl, (size_t)L_NLINES * 128) != hipSuccess ||
-        hipMalloc(&s->g_bar, (size_t)kMaxGridBlocks * 128) != hipSuccess)
-        return bail(fail(MCM_ENOMEM, "server control allocation failed"));
     if (prepare_match_wg(s->opt.wg_block) != hipSuccess) return bail(fail(MCM_EHIP, "kernel attribute failed"));
     s->st.budget_bytes = hbm_budget_bytes;
     s->t0 = Clock::now();
@@ -530,12 +505,11 @@ int64_t mcm_server_submit(mcm_server *s, int32_t ncols, int32_t nrows, const int
         s->st.completed += 1;
         return r->ticket;
     }
-    r->pin = s->pins.get();
-    if (!r->pin || hipEventCreateWithFlags(&r->ev_in, hipEventDisableTiming) != hipSuccess ||
+    if (hipEventCreateWithFlags(&r->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&r->ev_out, hipEventDisableTiming) != hipSuccess) {
-        s->pins.put(r->pin);
+        if (r->ev_in) (void)hipEventDestroy(r->ev_in);
         delete r;
-        return fail(MCM_EHIP, "event or pinned slot creation failed");
+        return fail(MCM_EHIP, "event creation failed");
     }
     s->live[r->ticket] = r;
     s->pending.push_back(r);
@@ -559,7 +533,6 @@ int64_t mcm_server_poll(mcm_server *s, int64_t ticket, mcm_request_info *info, d
     if (r->state != Q_DONE) return 0;
     if (info) *info = r->info;
     s->live.erase(it);
-    s->pins.put(r->pin);
     if (r->ev_in) (void)hipEventDestroy(r->ev_in);
     if (r->ev_out) (void)hipEventDestroy(r->ev_out);
     const int64_t card = r->info.card;
@@ -591,15 +564,12 @@ int mcm_server_destroy(mcm_server *s)
         delete r;
     }
     for (auto &sl : s->slots) {
-        for (void *q : {(void *)sl.d_desc, (void *)sl.d_card, (void *)sl.d_ctrl}) if (q) (void)hipFree(q);
+        for (void *q : {(void *)sl.d_desc, (void *)sl.d_card, (void *)sl.d_ctrl, (void *)sl.d_bar}) if (q) (void)hipFree(q);
         for (void *q : {(void *)sl.h_desc, (void *)sl.h_card, (void *)sl.h_ctrl}) if (q) (void)hipHostFree(q);
         if (sl.done) (void)hipEventDestroy(sl.done);
     }
-    if (s->g_ctrl) (void)hipFree(s->g_ctrl);
-    if (s->g_bar) (void)hipFree(s->g_bar);
     if (s->compute) (void)hipStreamDestroy(s->compute);
     if (s->copy) (void)hipStreamDestroy(s->copy);
-    s->pins.release();
     s->arena.release();
     delete s;
     return MCM_OK;

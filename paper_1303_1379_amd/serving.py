@@ -83,5 +83,5 @@ def replay(server: mcm.Server, pool, nreq: int, lam: float = 2000.0, seed: int =
     return {"requests": nreq, "warmup": warmup, "offered_rate": lam,
             "p50_ms": round(float(np.percentile(lw, 50)), 3), "p99_ms": round(float(np.percentile(lw, 99)), 3),
             "mean_ms": round(float(lw.mean()), 3), "graphs_per_s": round(nreq / makespan, 1),
-            "makespan_s": round(makespan, 3), "whole_device_requests": int(paths.sum()),
+            "makespan_s": round(makespan, 3), "multi_graph_requests": int(paths.sum()),
             "mean_batch": round(float(batch[paths == 0].mean()) if (paths == 0).any() else 0.0, 1)}

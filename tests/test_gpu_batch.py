@@ -18,7 +18,8 @@ from paper_1303_1379_amd import graphgen as gg, mcm  # noqa: E402
 @pytest.fixture(autouse=True)
 def _reset():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
-    defaults = dict(mapping="auto", autotune=0, tuning="", stats=0, wg_block=1024, batch_min=8)
+    defaults = dict(mapping="auto", autotune=0, tuning="", stats=0, wg_block=1024, batch_min=8,
+                    multi_threshold=1 << 15, multi_group=0)
     for k, v in defaults.items():
         mcm.set_option(k, v)
     yield
@@ -117,3 +118,30 @@ def test_device_cheap_init_is_maximal(name):
     assert not np.any((cmh[cols] == -1) & (rmh[rows] == -1)), "not maximal"
     card, _, _ = mcm.match(dg, cm, rm)
     assert card == O.hopcroft_karp(g, *O.cheap_init(g))[0]
+
+
+@pytest.mark.parametrize("group", [0, 8])
+def test_large_members_in_multi_graph_launches(group):
+    """Members above the size threshold go to groups of blocks, several per
+    cooperative launch (group 8: all of them in one launch; default group:
+    several launches); small members share the workgroup kernel.  Includes
+    large degenerate members: no rows, no edges."""
+    graphs = [gg.uniform(30000, 28000, 4, 31), gg.batch_member(5, 0, hi=3000), gg.grid5(200, 120, 100, 7),
+              gg.empty(40000, 0), gg.uniform(20000, 20000, 3, 32), gg.batch_member(5, 1, hi=3000),
+              gg.rmat(15, 8 << 15, 33, n_limit=30000), gg.empty(20000, 20000), gg.uniform(17000, 16000, 2, 34),
+              gg.permutation_plus_noise(18000, 3, 35), gg.batch_member(5, 2, hi=3000)]
+    big = [g.nc + g.nr > (1 << 15) for g in graphs]
+    assert sum(big) >= 6 and not all(big)
+    refs = [O.hopcroft_karp(g, *O.cheap_init(g))[0] for g in graphs]
+    b = mcm.pack_batch(graphs)
+    mcm.set_option("multi_group", group)
+    total, cards, cm, rm = mcm.match_batched(b)
+    torch.cuda.synchronize()
+    assert cards.tolist() == refs and total == sum(refs)
+    _check_outputs(graphs, cm, rm, cards)
+    # the same batch with every member on the workgroup kernel, twice in a row
+    mcm.set_option("multi_threshold", 0)
+    for _ in range(2):
+        total0, cards0, cm0, rm0 = mcm.match_batched(b)
+        assert cards0.tolist() == refs
+    _check_outputs(graphs, cm0, rm0, cards0)

@@ -26,7 +26,7 @@ def _ref(g):
 def _graphs():
     gs = [gg.uniform(3000, 2500, 4, 11), gg.grid5(96, 200, 150, 3), gg.rmat(13, 8 << 13, 12, n_limit=6000),
           gg.batch_member(4, 7, hi=20000), gg.uniform(1200, 1800, 2, 13), gg.permutation_plus_noise(2000, 2, 5),
-          gg.uniform(70000, 70000, 4, 21)]   # the last one exceeds the batched-path size: whole device
+          gg.uniform(70000, 70000, 4, 21)]   # above the batched-path size: multi-graph persistent launch
     return gs
 
 
@@ -47,7 +47,7 @@ def test_alone_equals_mix_equals_oracle():
         assert card == ref
         assert O.check_matching(g, cm, rm) == card
         alone.append(card)
-        assert info["path"] == (1 if g.nc + g.nr > (1 << 17) else 0)
+        assert info["path"] == (1 if g.nc + g.nr > (1 << 15) else 0)
     # the same requests, three copies each, submitted together
     tickets = [(i, s.submit(gs[i])) for _ in range(3) for i in range(len(gs))]
     for i, t in tickets:
@@ -56,9 +56,29 @@ def test_alone_equals_mix_equals_oracle():
         card, info, cm, rm = res
         assert card == alone[i] == refs[i]
         assert O.check_matching(gs[i], cm, rm) == card
+        assert info["path"] == (1 if gs[i].nc + gs[i].nr > (1 << 15) else 0)
+        assert 1 <= info["batch_size"] <= (8 if info["path"] == 1 else 256)
     st = s.stats()
     assert st["completed"] == st["submitted"] == len(gs) * 4
-    assert st["launches_grid"] >= 4 and st["max_batch_seen"] >= 2
+    assert st["launches_grid"] >= 2 and st["max_batch_seen"] >= 2
+    s.close()
+
+
+def test_large_requests_share_multi_graph_launches():
+    """Several large requests in flight together: every result exact, and
+    the multi-graph launches together carry all of them."""
+    gs = [gg.uniform(20000 + 1000 * k, 19000, 3, 40 + k) for k in range(6)]
+    refs = [_ref(g) for g in gs]
+    s = mcm.Server(2 << 30, max_batch=64)
+    tickets = [s.submit(g) for g in gs for _ in range(2)]
+    for k, t in enumerate(tickets):
+        card, info, cm, rm = s.poll(t, wait_ms=60000)
+        assert card == refs[k // 2]
+        assert O.check_matching(gs[k // 2], cm, rm) == card
+        assert info["path"] == 1
+        assert 1 <= info["batch_size"] <= 8
+    st = s.stats()
+    assert st["launches_grid"] <= len(tickets) and st["completed"] == len(tickets)
     s.close()
 
 
