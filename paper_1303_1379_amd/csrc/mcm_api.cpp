@@ -169,6 +169,8 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     r.small_max = (uint32_t)o.small_max;
     r.batch_min = (uint32_t)o.batch_min;
     r.split = (uint32_t)o.split;
+    r.level_entries = (uint32_t)o.level_entries;
+    r.idle_sleep = (uint32_t)o.idle_sleep;
     r.timeout = (uint64_t)(o.timeout_s * info.clock_khz * 1000.0);
     return r;
 }
@@ -243,6 +245,7 @@ uint32_t base_flags(const Options &o, int64_t nc, int64_t nnz_hint)
 {
     uint32_t f = 0;
     if (o.wr) f |= F_WR;
+    if (o.wr_late) f |= F_WR_LATE;
     if (o.apsb) f |= F_APSB;
     if (o.stats) f |= F_STATS;
     bool wave = o.mapping == 1;
@@ -428,6 +431,16 @@ int mcm_set_option(const char *key, const char *value)
         if (!as_int(0, (int64_t)1 << 30, &x) || (x != 0 && x < 64))
             return (int)fail(MCM_EINVAL, "split must be 0 or in [64, 2^30]");
         g_opt.split = (int)x;
+    } else if (k == "level_entries") {
+        if (!as_int(0, 1 << 30, &x)) return (int)fail(MCM_EINVAL, "level_entries must be in [0, 2^30]");
+        g_opt.level_entries = (int)x;
+    } else if (k == "wr_check") {
+        if (v == "late") g_opt.wr_late = true;
+        else if (v == "early") g_opt.wr_late = false;
+        else return (int)fail(MCM_EINVAL, "wr_check must be early or late");
+    } else if (k == "idle_sleep") {
+        if (!as_int(0, 4096, &x)) return (int)fail(MCM_EINVAL, "idle_sleep must be in [0, 4096]");
+        g_opt.idle_sleep = (int)x;
     } else if (k == "multi_threshold") {
         if (!as_int(0, (int64_t)1 << 40, &x)) return (int)fail(MCM_EINVAL, "multi_threshold must be >= 0");
         g_opt.multi_threshold = x;
@@ -470,6 +483,9 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "wg_threshold") v = std::to_string(o.wg_threshold);
     else if (k == "small_max") v = std::to_string(o.small_max);
     else if (k == "multi_threshold") v = std::to_string(o.multi_threshold);
+    else if (k == "level_entries") v = std::to_string(o.level_entries);
+    else if (k == "idle_sleep") v = std::to_string(o.idle_sleep);
+    else if (k == "wr_check") v = o.wr_late ? "late" : "early";
     else if (k == "multi_group") v = std::to_string(o.multi_group);
     else if (k == "batch_min") v = std::to_string(o.batch_min);
     else if (k == "split") v = std::to_string(o.split);

@@ -56,6 +56,7 @@ const std::string &last_error();
 struct Options {
     bool apsb = false;        // driver
     bool wr = true;           // bfs
+    bool wr_late = true;      // WR root check beside the edge visit (wave mapping)
     int mapping = 2;          // 0 thread, 1 wave, 2 auto
     int loop = 2;             // 0 device, 1 host, 2 auto
     bool validate = false;
@@ -70,6 +71,8 @@ struct Options {
     int64_t small_max = 256;  // frontiers up to this size are expanded by one workgroup
     int batch_min = 8;        // fewest frontier entries per wavefront batch
     int split = 64;           // heavier columns enter the frontier in pieces of this many edges (0 = off)
+    int level_entries = 128;  // grid levels: one block per this many frontier entries (0 = all blocks)
+    int idle_sleep = 8;       // barrier polls of blocks that sat a level out: s_sleep(1) count between
     int64_t multi_threshold = 1 << 15;  // batch members with nc + nr above this: multi-graph launches (0 = never)
     int multi_group = 0;      // blocks per graph in a multi-graph launch (0 = CUs / 4)
     double timeout_s = 20.0;  // device barrier wait limit

@@ -9,7 +9,7 @@ namespace mcm {
 // another.
 enum CtrlLine : int {
     L_QUEUE = 0,       // graph queue head of the one-workgroup-per-graph kernel
-    L_BAR_GEN,         // grid barrier: epoch released by block 0
+    L_BAR_GEN,         // grid barrier: epoch and loop state released by block 0 (two 64-bit words)
     L_FCOUNT0,         // frontier sizes, rotating over three levels
     L_FCOUNT1,
     L_FCOUNT2,
@@ -21,8 +21,6 @@ enum CtrlLine : int {
     L_PHASE,           // phases run (== stamp of the last phase)
     L_LEVELS,          // BFS levels expanded, all phases
     L_CARD,            // |M| (64-bit)
-    L_CURLEVEL,        // level reached by a run of single-workgroup levels
-    L_STOP,            // that run ended on a level that reached an unmatched row (APsB)
     L_SMALL_LEVELS,    // levels expanded by single-workgroup runs (counter)
     L_STAT0,           // stats counters (64-bit each, own lines)
     L_NLINES = L_STAT0 + 12
@@ -41,7 +39,8 @@ enum Flags : uint32_t {
     F_STATS = 4u,     // count edges, claims, ...
     F_LEVELS = 8u,    // record column levels (inspection mode)
     F_NOAUG = 16u,    // one BFS phase only, no Alternate/Fix (levels, cover)
-    F_WAVE = 32u      // wave-balanced edge mapping (else one column per lane)
+    F_WAVE = 32u,     // wave-balanced edge mapping (else one column per lane)
+    F_WR_LATE = 64u   // WR root check with the edge visit, off the load chain (wave mapping)
 };
 
 // Device view of one graph plus its working state.
@@ -67,6 +66,9 @@ struct RunOpt {
     uint32_t batch_min;    // fewest frontier entries a wavefront takes per batch (1..64)
     uint32_t split;        // a column with more edges enters the frontier as several entries of at
                            // most `split` edges each (0 = never; queue capacity must allow it)
+    uint32_t level_entries;  // grid levels: one block per this many frontier entries takes part
+                             // (the rest wait for the level's end); 0 = every block, every level
+    uint32_t idle_sleep;   // polls of a barrier waiter that did not arrive are this many s_sleep(1) apart
     uint64_t timeout;      // wall-clock ticks a grid barrier may wait
 };
 

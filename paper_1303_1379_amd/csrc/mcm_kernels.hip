@@ -115,6 +115,7 @@ struct Stage {
     int4 *q;      // LDS [kStageQ] frontier entries of this wavefront
     int32_t *e;   // LDS [kStageE] unmatched-row ends
     int nq, ne;   // fill (wavefront-uniform)
+    int dq, de;   // entries already handed to the global queues since the last flush
 };
 
 DEV Stage make_stage(char *smem)
@@ -124,6 +125,7 @@ DEV Stage make_stage(char *smem)
     s.q = reinterpret_cast<int4 *>(smem) + w * kStageQ;
     s.e = reinterpret_cast<int32_t *>(smem + waves * kStageQ * 16) + w * kStageE;
     s.nq = s.ne = 0;
+    s.dq = s.de = 0;
     return s;
 }
 
@@ -134,7 +136,7 @@ DEV uint32_t *stage_tmp(char *smem)
 }
 
 template <class T>
-DEV void stage_drain(T *buf, int &n, T *gq, uint32_t *gcnt)
+DEV void stage_drain(T *buf, int &n, T *gq, uint32_t *gcnt, int &drained)
 {
     wave_lds_sync();
     uint32_t base = 0;
@@ -142,45 +144,61 @@ DEV void stage_drain(T *buf, int &n, T *gq, uint32_t *gcnt)
     base = __shfl(base, 0, 64);
     for (int i = __lane_id(); i < n; i += 64) gq[base + i] = buf[i];
     wave_lds_sync();
+    drained += n;
     n = 0;
 }
 
 // Append `item` for every lane with p set (wavefront-uniform call).
 template <class T, int CAP>
-DEV void stage_push(bool p, const T &item, T *buf, int &n, T *gq, uint32_t *gcnt)
+DEV void stage_push(bool p, const T &item, T *buf, int &n, T *gq, uint32_t *gcnt, int &drained)
 {
     const uint64_t m = __ballot(p);
     if (m == 0) return;
-    if (n > CAP - 64) stage_drain(buf, n, gq, gcnt);
+    if (n > CAP - 64) stage_drain(buf, n, gq, gcnt, drained);
     if (p) buf[n + __popcll(m & lanemask_lt())] = item;
     n += __popcll(m);
 }
 
 // End of a level: every wavefront of the workgroup hands its staged entries
 // to the global queues with one atomic per queue for the whole workgroup.
-// All threads of the workgroup call it.
-DEV void block_flush(Stage &st, int4 *gq, uint32_t *gqcnt, int32_t *ge, uint32_t *gecnt, uint32_t *s_tmp)
+// All threads of the workgroup call it.  Returns what the workgroup added
+// since the last flush: frontier entries in the low 31 bits, bit 31 set if
+// it added any unmatched-row end.
+DEV uint32_t block_flush(Stage &st, int4 *gq, uint32_t *gqcnt, int32_t *ge, uint32_t *gecnt, uint32_t *s_tmp)
 {
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = __lane_id();
     wave_lds_sync();
-    if (lane == 0) { s_tmp[w] = (uint32_t)st.nq; s_tmp[16 + w] = (uint32_t)st.ne; }
+    if (lane == 0) {
+        s_tmp[w] = (uint32_t)st.nq;
+        s_tmp[16 + w] = (uint32_t)st.ne;
+        s_tmp[36 + w] = (uint32_t)(st.dq + st.nq) | ((st.de + st.ne) > 0 ? 0x80000000u : 0u);
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tq = 0, te = 0;
-        for (int i = 0; i < nw; ++i) {
-            const uint32_t a = s_tmp[i], b = s_tmp[16 + i];
-            s_tmp[i] = tq; tq += a;
-            s_tmp[16 + i] = te; te += b;
+    if (w == 0) {
+        // exclusive prefix of the per-wavefront counts by a wavefront scan
+        const int a = lane < nw ? (int)s_tmp[lane] : 0, b = lane < nw ? (int)s_tmp[16 + lane] : 0;
+        const uint32_t d = lane < nw ? s_tmp[36 + lane] : 0u;
+        const int ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+        const uint32_t tq = (uint32_t)__shfl(ia, 63, 64), te = (uint32_t)__shfl(ib, 63, 64);
+        const uint32_t added = (uint32_t)wave_sum((uint64_t)(d & 0x7fffffffu));
+        const bool any_end = __ballot((d >> 31) != 0) != 0;
+        uint32_t bq = 0, be = 0;
+        if (lane == 0) {
+            if (tq) bq = atomicAdd(gqcnt, tq);
+            if (te) be = atomicAdd(gecnt, te);
         }
-        s_tmp[32] = tq ? atomicAdd(gqcnt, tq) : 0u;
-        s_tmp[33] = te ? atomicAdd(gecnt, te) : 0u;
+        if (lane < nw) { s_tmp[lane] = (uint32_t)(ia - a); s_tmp[16 + lane] = (uint32_t)(ib - b); }
+        if (lane == 0) { s_tmp[32] = bq; s_tmp[33] = be; s_tmp[34] = added | (any_end ? 0x80000000u : 0u); }
     }
     __syncthreads();
     const uint32_t bq = s_tmp[32] + s_tmp[w], be = s_tmp[33] + s_tmp[16 + w];
+    const uint32_t res = s_tmp[34];
     for (int i = lane; i < st.nq; i += 64) gq[bq + i] = st.q[i];
     for (int i = lane; i < st.ne; i += 64) ge[be + i] = st.e[i];
     st.nq = st.ne = 0;
+    st.dq = st.de = 0;
     __syncthreads();
+    return res;
 }
 
 // ---------------------------------------------------------------------
@@ -276,7 +294,7 @@ DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, int4 *gq, 
 {
     const bool heavy = p && split != 0 && (uint32_t)(e.w - e.z) > split;
     if (__ballot(heavy) == 0) {
-        stage_push<int4, kStageQ>(p, e, st.q, st.nq, gq, gcnt);
+        stage_push<int4, kStageQ>(p, e, st.q, st.nq, gq, gcnt, st.dq);
         return;
     }
     const int nch = p ? (heavy ? (int)((e.w - e.z + split - 1) / split) : 1) : 0;
@@ -284,29 +302,40 @@ DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, int4 *gq, 
     for (int k = 0; k < maxk; ++k) {
         const int b = e.z + k * (int)split;
         const int en = heavy ? min(e.w, b + (int)split) : e.w;
-        stage_push<int4, kStageQ>(k < nch, make_int4(e.x, e.y, b, en), st.q, st.nq, gq, gcnt);
+        stage_push<int4, kStageQ>(k < nch, make_int4(e.x, e.y, b, en), st.q, st.nq, gq, gcnt, st.dq);
     }
 }
 
 template <bool WAVE, int S>
-DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
-                      int level, const RunOpt &o, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc)
+DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
+                          int level, const RunOpt &o, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc)
 {
     const int lane = __lane_id();
     const uint32_t flags = o.flags;
     const uint64_t t0 = (flags & F_STATS) ? wall_clock64() : 0;
     bool any_end = false;
     const uint32_t B = batch_size(n, nwaves, o.batch_min);
+    // WR: a root that already has a path expands nothing more.  Early: the
+    // entry's edges are dropped before the scan (fewer edges, but the scan
+    // waits for the cdone load); late (wave mapping): the scan and the
+    // rowind loads go ahead and the claims of such an entry are skipped.
+    const bool late = WAVE && (flags & F_WR) && (flags & F_WR_LATE);
     for (uint32_t base = wave * B; base < n; base += nwaves * B) {
         const uint32_t i = base + lane;
         int4 e = make_int4(0, 0, 0, 0);
         int deg = 0;
+        uint32_t rdone = 0;
         if ((uint32_t)lane < B && i < n) {
             e = fq[i];
             deg = e.w - e.z;
-            if ((flags & F_WR) && deg > 0 && g.cdone[e.y] == ph) deg = 0;  // root already has a path
+            if (late) rdone = g.cdone[e.y];
+            else if ((flags & F_WR) && deg > 0 && g.cdone[e.y] == ph) deg = 0;
         }
-        if (flags & F_STATS) { acc.edges += deg; acc.expanded += (deg > 0); }
+        if (flags & F_STATS) {
+            const bool live = !(late && rdone == ph);
+            acc.edges += live ? deg : 0;
+            acc.expanded += (live && deg > 0);
+        }
         if (WAVE) {
             const int incl = wave_incl_scan(deg);
             const int excl = incl - deg;
@@ -329,10 +358,11 @@ DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wa
                 int r = 0;
                 if (k < total) {
                     r = g.rowind[obeg + (k - oexcl)];
-                    visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend);
+                    const uint32_t odone = late ? (uint32_t)__shfl((int)rdone, own, 64) : 0u;
+                    if (!late || odone != ph) visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend);
                 }
                 push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
-                stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt);
+                stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt, st.de);
                 any_end |= newend;
                 if (flags & F_STATS) { acc.claimed += newcol; acc.found += newend; }
             }
@@ -347,7 +377,7 @@ DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wa
                     visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend);
                 }
                 push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
-                stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt);
+                stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt, st.de);
                 any_end |= newend;
                 if (flags & F_STATS) { acc.claimed += newcol; acc.found += newend; }
             }
@@ -355,8 +385,9 @@ DEV void expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wa
     }
     if ((flags & F_APSB) && __ballot(any_end) != 0 && lane == 0) atomicOr(io.found, 1u);
     const uint64_t t1 = (flags & F_STATS) ? wall_clock64() : 0;
-    block_flush(st, io.nfq, io.ncnt, g.ends, io.ecnt, s_tmp);
+    const uint32_t added = block_flush(st, io.nfq, io.ncnt, g.ends, io.ecnt, s_tmp);
     if (flags & F_STATS) { acc.t_expand += t1 - t0; acc.t_flush += wall_clock64() - t1; }
+    return added;
 }
 
 // InitBfsArray (paper, section 3, before Algorithm 2; root filled as in
@@ -428,59 +459,149 @@ DEV void fix_matching(const DevGraph &g, uint32_t tid, uint32_t nthreads, uint32
 }
 
 // ---------------------------------------------------------------------
-// Grid barrier of the cooperative launch.  Every block but 0 publishes its
-// arrival in its own flag line (no shared counter, no contention); wave 0
-// of block 0 polls all flags, then releases the epoch.  Agent-scope release
-// before arriving, acquire after leaving; every wait is bounded.  Returns
-// false (in all blocks, eventually) once any block set a status.
+// Grid barrier of the cooperative launch.  Blocks 1 .. active-1 publish
+// their arrival in their own flag line (no shared counter, no contention);
+// wave 0 of block 0 polls those flags and then releases the next epoch
+// together with the state of the level loop (level L, frontier size n, APsB
+// stop flag), which it reads from counters once every arrival is in, or is
+// given.  Blocks at or above `active` did nothing since their last barrier
+// and do not arrive: block 0 may release further epochs before they look,
+// so the state travels with the epoch and a late block adopts the latest
+// one.  Two 64-bit words carry it: B = {epoch, L | stop << 31} is stored
+// first, then A = {epoch, n} with release; a reader takes A, then B, and
+// accepts the pair when both name the same epoch.  Agent-scope release
+// before arriving; acquire after leaving, but only where `touches(state)`
+// says the block will read data the others wrote before its next barrier
+// (an acquire invalidates the XCD's L2 under the blocks still working
+// there, so the blocks that sit the next level out skip it; their next
+// acquire, when they take part again, orders everything released before).
+// Every wait is bounded.  Returns false (in all blocks, eventually) once
+// any block set a status.
 // The blocks that synchronise: block `b` of a group of `n` (the whole grid,
 // or one graph's share of a multi-graph launch).
 struct Grp {
     uint32_t b, n;
 };
 
-DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t timeout, int *s_ok, Grp gr)
+struct LvState {
+    uint32_t L, n, stop;
+};
+
+// What block 0 releases: L, and n and stop either given or read from a
+// counter once every arrival is in; with `sum`, n and stop are block 0's
+// own share, and every arriving block adds its share (carried in its
+// arrival word: entries added in the low 31 bits, bit 31 = reached an
+// unmatched row and the loop stops there).
+struct Pub {
+    uint32_t L, n, stop;
+    const uint32_t *n_ptr, *stop_ptr;
+    bool sum;
+};
+
+template <class Touches>
+DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t timeout, int *s_ok, Grp gr,
+                      uint32_t active, uint32_t idle_sleep, const Pub &pub, uint32_t share, Touches touches,
+                      uint32_t *s_st, LvState *out)
 {
     __syncthreads();
     ++epoch;
-    uint32_t *gen = line(ctrl, L_BAR_GEN);
+    uint64_t *wa = reinterpret_cast<uint64_t *>(line(ctrl, L_BAR_GEN));
+    uint64_t *wb = reinterpret_cast<uint64_t *>(line(ctrl, L_BAR_GEN) + 16);
     if (gr.b == 0) {
         if (threadIdx.x < 64) {
             int ok = status_of(ctrl) == 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const uint64_t t0 = wall_clock64();
+            uint64_t added = 0;
+            bool ended = false;
             while (ok) {
                 bool mine = true;
-                for (uint32_t b = 1 + threadIdx.x; b < gr.n; b += 64)
-                    mine &= ld_u<kAgent>(bar + (size_t)b * kLineWords) == epoch;
+                added = 0;
+                ended = false;
+                for (uint32_t b = 1 + threadIdx.x; b < active; b += 64) {
+                    const uint64_t v = __hip_atomic_load(reinterpret_cast<uint64_t *>(bar + (size_t)b * kLineWords),
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    mine &= (uint32_t)v == epoch;
+                    added += (v >> 32) & 0x7fffffffu;
+                    ended |= (v >> 63) != 0;
+                }
                 if (__ballot(!mine) == 0) break;
                 if (status_of(ctrl) != 0) ok = 0;
                 else if (wall_clock64() - t0 > timeout) { if (threadIdx.x == 0) set_status(ctrl, kEInternal); ok = 0; }
                 __builtin_amdgcn_s_sleep(1);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const uint32_t all_added = (uint32_t)wave_sum(added);
+            const bool any_ended = __ballot(ended) != 0;
             if (threadIdx.x == 0) {
-                if (ok) __hip_atomic_store(gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t n = pub.n_ptr ? ld_u<kAgent>(pub.n_ptr) : pub.n;
+                uint32_t stop = pub.stop_ptr ? (uint32_t)(ld_u<kAgent>(pub.stop_ptr) != 0) : pub.stop;
+                if (pub.sum) {
+                    n += all_added;
+                    stop |= any_ended ? 1u : 0u;
+                }
+                if (ok) {
+                    __hip_atomic_store(wb, ((uint64_t)(pub.L | stop << 31) << 32) | epoch, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(wa, ((uint64_t)n << 32) | epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                s_st[0] = pub.L;
+                s_st[1] = n;
+                s_st[2] = stop;
+                s_st[3] = epoch;
                 *s_ok = ok;
             }
         }
     } else if (threadIdx.x == 0) {
         int ok = status_of(ctrl) == 0;
+        s_st[3] = epoch;
         if (ok) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(bar + (size_t)gr.b * kLineWords, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (gr.b < active) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(reinterpret_cast<uint64_t *>(bar + (size_t)gr.b * kLineWords),
+                                   ((uint64_t)share << 32) | epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             const uint64_t t0 = wall_clock64();
-            while (ld_u<kAgent>(gen) != epoch) {
+            for (;;) {
+                const uint64_t a = __hip_atomic_load(wa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((int32_t)((uint32_t)a - epoch) >= 0) {
+                    // only a pair naming one epoch is taken: a stale B (or a
+                    // newer one) sends the reader round again
+                    const uint64_t w = __hip_atomic_load(wb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((uint32_t)w == (uint32_t)a) {
+                        const LvState x{(uint32_t)(w >> 32) & 0x7fffffffu, (uint32_t)(a >> 32), (uint32_t)(w >> 63)};
+                        if (touches(x)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        s_st[0] = x.L;
+                        s_st[1] = x.n;
+                        s_st[2] = x.stop;
+                        s_st[3] = (uint32_t)a;
+                        break;
+                    }
+                    continue;  // block 0 moved on between the two loads: read both again
+                }
                 if (status_of(ctrl) != 0) { ok = 0; break; }
                 if (wall_clock64() - t0 > timeout) { set_status(ctrl, kEInternal); ok = 0; break; }
-                __builtin_amdgcn_s_sleep(1);
+                // a block that did not arrive polls less often: many of them
+                // polling one line slow every other access of the level
+                if (gr.b < active) __builtin_amdgcn_s_sleep(1);
+                else for (uint32_t k = 0; k < idle_sleep; ++k) __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         *s_ok = ok;
     }
     __syncthreads();
+    *out = LvState{s_st[0], s_st[1], s_st[2]};
+    epoch = s_st[3];
     return *s_ok != 0;
+}
+
+// Blocks that expand a grid level of n entries: one per `per` entries
+// (per = 0: every block).
+DEV uint32_t level_blocks(uint32_t n, uint32_t per, uint32_t nblocks)
+{
+    if (per == 0) return nblocks;
+    const uint32_t a = (n + per - 1) / per;
+    return a < 1 ? 1u : (a > nblocks ? nblocks : a);
 }
 
 // ---------------------------------------------------------------------
@@ -489,15 +610,16 @@ DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t t
 // entries in the current queue, stops when the frontier is empty or larger
 // than small_max (or, APsB, after a level that reached an unmatched row).
 // Counters live in LDS (s_loc[0..2] frontier sizes, [3] found, [4] ends)
-// and are written back to the control block at the end, with the level
-// reached in L_CURLEVEL.  Returns the number of levels expanded.
+// and the frontier counters are written back to the control block at the
+// end.  Returns the state reached (level, its frontier size, APsB stop);
+// *levels grows by the number of levels expanded.
 // Bound on one run, so that the blocks waiting at the grid barrier see
 // progress well within their wait limit.
 constexpr uint32_t kSmallRunLevels = 4096;
 
 template <bool WAVE>
-DEV uint32_t small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t ph, int L, uint32_t n0,
-                          Stage &st, uint32_t *s_tmp, uint32_t *s_loc, Acc &acc)
+DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t ph, int L, uint32_t n0,
+                         Stage &st, uint32_t *s_tmp, uint32_t *s_loc, Acc &acc, uint32_t *total_levels)
 {
     const uint32_t flags = o.flags;
     if (threadIdx.x == 0) {
@@ -525,17 +647,17 @@ DEV uint32_t small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, ui
         ++L;
     }
     __syncthreads();
+    const uint32_t n = s_loc[L % 3];
     if (threadIdx.x == 0) {
         for (int i = 0; i < 3; ++i) {
-            *line(ctrl, L_FCOUNT0 + i) = (i == L % 3) ? s_loc[L % 3] : 0u;
+            *line(ctrl, L_FCOUNT0 + i) = (i == L % 3) ? n : 0u;
             *line(ctrl, L_FOUND0 + i) = 0;
         }
         *line(ctrl, L_NENDS) = s_loc[4];
-        *line(ctrl, L_CURLEVEL) = (uint32_t)L;
-        *line(ctrl, L_STOP) = stop;
         *line(ctrl, L_SMALL_LEVELS) += levels;
     }
-    return levels;
+    *total_levels += levels;
+    return LvState{(uint32_t)L, n, stop};
 }
 
 // The phase loop of Algorithm 1 over the whole grid (cooperative launch).
@@ -553,53 +675,78 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     uint32_t epoch = 0, total_levels = 0, ph = 1;
     auto fc = [&](int i) { return line(ctrl, L_FCOUNT0 + i); };
     auto fd = [&](int i) { return line(ctrl, L_FOUND0 + i); };
-    // grid barrier, with the time block 0 spends in it counted (stats=1)
-    auto sync = [&]() -> bool {
+    // grid barrier (`active` blocks arrive; block 0 releases the loop state
+    // `p` into s), with the time block 0 spends in it counted (stats=1)
+    LvState s{0, 0, 0};
+    // does this block read shared data before its next barrier in state x?
+    // (it expands the level, or the level loop ends and Alternate follows)
+    auto in_level = [&](const LvState &x) -> bool {
+        if (x.n == 0 || x.stop) return true;
+        if (x.n <= o.small_max) return gr.b == 0;
+        return gr.b < level_blocks(x.n, o.level_entries, gr.n);
+    };
+    auto always = [](const LvState &) -> bool { return true; };
+    auto sync = [&](uint32_t active, const Pub &p, uint32_t share) -> bool {
         const uint64_t t0 = timing ? wall_clock64() : 0;
-        const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr);
+        const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr, active, o.idle_sleep, p, share, in_level,
+                                     s_loc + 8, &s);
         if (timing) acc.t_barrier += wall_clock64() - t0;
         return ok;
     };
+    auto sync_all = [&](const Pub &p) -> bool {
+        const uint64_t t0 = timing ? wall_clock64() : 0;
+        const bool ok =
+            grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr, gr.n, o.idle_sleep, p, 0u, always, s_loc + 8, &s);
+        if (timing) acc.t_barrier += wall_clock64() - t0;
+        return ok;
+    };
+    const Pub none{0, 0, 0, nullptr, nullptr, false};
     for (;; ++ph) {
         if (ph > o.max_phases) { if (leader) set_status(ctrl, kEInternal); return false; }
         init_roots(g, wave, nwaves, o, fc(0), st, s_tmp, acc);
-        if (!sync()) return false;
-        int L = 0;
+        if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
         for (;;) {
-            const uint32_t n = ld_u<kAgent>(fc(L % 3));
-            if (n == 0) break;
+            const int L = (int)s.L;
+            if (s.n == 0 || s.stop) break;
             if ((uint32_t)L > o.max_levels) { if (leader) set_status(ctrl, kEInternal); return false; }
-            if (n <= o.small_max) {
+            if (s.n <= o.small_max) {
+                Pub p = none;
                 if (gr.b == 0) {
                     const uint64_t t0 = timing ? wall_clock64() : 0;
-                    total_levels += small_levels<WAVE>(g, ctrl, o, ph, L, n, st, s_tmp, s_loc, acc);
+                    const LvState r = small_levels<WAVE>(g, ctrl, o, ph, L, s.n, st, s_tmp, s_loc, acc, &total_levels);
                     if (timing) acc.t_small += wall_clock64() - t0;
+                    p = Pub{r.L, r.n, r.stop, nullptr, nullptr, false};
                 }
-                if (!sync()) return false;
-                L = (int)ld_u<kAgent>(line(ctrl, L_CURLEVEL));
-                if ((flags & F_APSB) && ld_u<kAgent>(line(ctrl, L_STOP))) break;
+                if (!sync(1, p, 0u)) return false;
                 continue;
             }
+            const uint32_t active = level_blocks(s.n, o.level_entries, gr.n);
             if (leader) { *fc((L + 2) % 3) = 0; *fd((L + 2) % 3) = 0; }
-            const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
-            LevelIO io{(L & 1) ? g.fq0 : g.fq1, fc((L + 1) % 3), line(ctrl, L_NENDS), fd(L % 3)};
-            expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
+            // this block's share of the next frontier (and, APsB, whether it
+            // reached an unmatched row) rides on its arrival
+            uint32_t share = 0;
+            if (gr.b < active) {
+                const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
+                LevelIO io{(L & 1) ? g.fq0 : g.fq1, fc((L + 1) % 3), line(ctrl, L_NENDS), fd(L % 3)};
+                share = expand_level<WAVE, kAgent>(g, cur, s.n, wave, active * (blockDim.x >> 6), ph, L, o, io, st,
+                                                   s_tmp, acc);
+                if (!(flags & F_APSB)) share &= 0x7fffffffu;
+            }
             ++total_levels;
-            if (!sync()) return false;
-            if ((flags & F_APSB) && ld_u<kAgent>(fd(L % 3)) != 0) break;
-            ++L;
+            if (!sync(active, Pub{(uint32_t)L + 1, share & 0x7fffffffu, share >> 31, nullptr, nullptr, true}, share))
+                return false;
         }
         const uint32_t ne = ld_u<kAgent>(line(ctrl, L_NENDS));
         if (ne == 0 || (flags & F_NOAUG)) break;
         const uint64_t ta = timing ? wall_clock64() : 0;
         alternate<kAgent>(g, ne, tid, nthreads, flags, ctrl, acc);
-        if (!sync()) return false;
+        if (!sync_all(none)) return false;
         fix_matching(g, tid, nthreads, flags, acc);
         if (leader) {
             for (int i = 0; i < 3; ++i) { *fc(i) = 0; *fd(i) = 0; }
             *line(ctrl, L_NENDS) = 0;
         }
-        if (!sync()) return false;
+        if (!sync_all(none)) return false;
         if (timing) acc.t_augment += wall_clock64() - ta;
     }
     if (leader) { *ph_out = ph; *lv_out = total_levels; }
@@ -710,7 +857,7 @@ __global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl,
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_ok;
-    __shared__ uint32_t s_loc[8];
+    __shared__ uint32_t s_loc[12];
     Stage st = make_stage(smem);
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
@@ -773,7 +920,7 @@ __global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *desc
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_ok;
-    __shared__ uint32_t s_loc[8];
+    __shared__ uint32_t s_loc[12];
     const uint32_t gi = blockIdx.x / group;
     if (gi >= (uint32_t)ngraphs) return;  // whole block: never part of any barrier
     const Grp gr{blockIdx.x % group, group};
@@ -920,7 +1067,7 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
                                                    int64_t *card, uint32_t *ctrl, RunOpt o)
 {
     extern __shared__ __align__(16) char smem[];
-    __shared__ uint32_t s_loc[8];
+    __shared__ uint32_t s_loc[12];
     __shared__ int32_t s_next;
     __shared__ uint32_t s_m;
     Stage st = make_stage(smem);

@@ -26,7 +26,8 @@ DRIVER_COMBOS = [
     dict(driver="apsb", bfs="wr", mapping="thread", loop="host"),
 ]
 
-DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384)
+DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
+                level_entries=128, idle_sleep=8, wr_check="late", small_max=256)
 
 
 @pytest.fixture(autouse=True)
@@ -190,6 +191,28 @@ def test_driver_variants(combo, name):
         _set(wg_threshold=thr, **combo)
         card, _, _ = _gpu(g)
         assert card == ref, (combo, thr)
+
+
+# Grid levels with a varying number of participating blocks: every block
+# (0), one block per frontier entry (1), few blocks (4096); no single-workgroup
+# runs (small_max 0: every level crosses the grid barrier); APsB carries its
+# stop flag through the barrier; both places of the WR root check.
+ELASTIC = [dict(level_entries=0, idle_sleep=1, small_max=256, driver="apfb", wr_check="late"),
+           dict(level_entries=1, idle_sleep=0, small_max=0, driver="apfb", wr_check="late"),
+           dict(level_entries=64, idle_sleep=1, small_max=0, driver="apsb", wr_check="early"),
+           dict(level_entries=4096, idle_sleep=64, small_max=256, driver="apsb", wr_check="late"),
+           dict(level_entries=4096, idle_sleep=8, small_max=0, driver="apfb", wr_check="early")]
+
+
+@pytest.mark.parametrize("combo", ELASTIC, ids=lambda c: "-".join(str(v) for v in c.values()))
+@pytest.mark.parametrize("name", ["grid256", "rmat15", "uniform2000"])
+def test_elastic_grid_levels(combo, name):
+    g = gg.workload(name)
+    ref = _oracle_card(g)
+    _set(wg_threshold=0, loop="device", **combo)
+    card, _, _ = _gpu(g)
+    assert card == ref, combo
+    assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty")
 
 
 @pytest.mark.parametrize("name,init", [("grid256", "cheap"), ("grid200", "empty"), ("rmat15", "cheap"),
