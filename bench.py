@@ -153,6 +153,69 @@ def bench_serving(pool_size, nreq, warmup, lam):
     return r
 
 
+VARIANTS = [(drv, bfs, mp, ep) for drv in ("apfb", "apsb") for bfs in ("wr", "plain") for mp in ("wave", "thread")
+            for ep in (("all", "one") if bfs == "wr" else ("all",))]
+
+
+def bench_variants(names, reps):
+    """The paper's variant grid on each workload: driver APFB / APsB x BFS
+    GPUBFS-WR / GPUBFS x edge mapping (edges of a wavefront batch dealt over
+    its lanes / one column per lane), and for WR Alternate from every
+    reached unmatched row or from one per root; each from the same greedy
+    matching; median HIP-event matching time of `reps` runs, counters from
+    one more."""
+    import numpy as np
+    import torch
+    from paper_1303_1379_amd import graphgen as gg, mcm
+    rows = []
+    for name in names:
+        g = gg.workload(name)
+        _, cm0, rm0 = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)
+        dg = mcm.to_device(g)
+        icm, irm = torch.from_numpy(cm0).cuda(), torch.from_numpy(rm0).cuda()
+        cards = set()
+        for drv, bfs, mp, ep in VARIANTS:
+            for k, v in (("driver", drv), ("bfs", bfs), ("mapping", mp), ("endpoints", ep), ("stats", 1)):
+                mcm.set_option(k, v)
+            card, _, _ = mcm.match(dg, icm, irm)
+            st = mcm.last_stats()
+            mcm.set_option("stats", 0)
+            ms = []
+            for _ in range(reps):
+                mcm.match(dg, icm, irm)
+                ms.append(mcm.last_stats()["kernel_ms"])
+            cards.add(card)
+            rows.append({"workload": name, "driver": drv, "bfs": bfs, "mapping": mp, "endpoints": ep, "card": card,
+                         "ms_median": round(float(np.median(ms)), 3), "phases": st["phases"],
+                         "levels": st["levels"], "edges_scanned": st["edges_scanned"],
+                         "alt_steps": st["alt_steps"], "fix_resets": st["fix_resets"],
+                         "edges_per_s": round(st["edges_scanned"] / (float(np.median(ms)) / 1e3), 1)})
+        assert len(cards) == 1, f"{name}: variants disagree on |M|: {cards}"
+    for k, v in (("driver", "apfb"), ("bfs", "wr"), ("mapping", "auto"), ("endpoints", "auto")):
+        mcm.set_option(k, v)
+    return rows
+
+
+def measured_copy_gbs(nbytes=1 << 30, reps=5):
+    """Device copy bandwidth: one elementwise kernel reading and writing
+    nbytes each, timed with events on torch's stream (the stream it runs on)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(reps):
+        e0.record()
+        torch.neg(a, out=b)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return round(2 * nbytes / (best / 1e3) / 1e9, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +229,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--variants", default="",
+                    help="instead of the bench line: the APFB/APsB x WR/plain x wave/thread grid on these "
+                         "comma-separated workloads (one JSON line)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of matching, stream this many bytes through one elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -181,6 +247,14 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+
+    if args.variants:
+        names = [w for w in args.variants.split(",") if w]
+        for w in names:
+            if w not in WORKLOADS:
+                ap.error(f"unknown workload {w}")
+        print(json.dumps({"variants": bench_variants(names, max(args.steps, 1))}), flush=True)
+        return
 
     if args.copy_bytes:
         n = args.copy_bytes // 4
@@ -262,7 +336,8 @@ def main():
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                            "kernel": "k_persistent<true>", "alg_bytes_per_launch": int(b),
-                           "avg_launch_ms": round(avg_k * 1000.0, 4)}
+                           "avg_launch_ms": round(avg_k * 1000.0, 4),
+                           "measured_copy_gbs": measured_copy_gbs()}
         out["block0_ms"] = {k: round(stats[k], 2) for k in ("t_expand_ms", "t_flush_ms", "t_barrier_ms",
                                                              "t_small_ms", "t_augment_ms")}
     out["setup_s"] = {"generate": round(t_gen, 2)}

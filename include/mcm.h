@@ -279,6 +279,15 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              that finds an unmatched row
  *   "bfs"       "wr" (default) | "plain"       GPUBFS-WR (Algorithm 4) or
  *                                              GPUBFS (Algorithm 2)
+ *   "endpoints" "auto" (default) | "one" | "all"
+ *                                              with WR: Alternate starts
+ *                                              from one reached unmatched
+ *                                              row per root (the first), or
+ *                                              from all of them; auto = one
+ *                                              under APsB, all under APFB
+ *                                              (section 3, the improvement
+ *                                              of GPUBFS-WR with root and
+ *                                              bfs_array)
  *   "mapping"   "auto" (default) | "thread" | "wave"
  *                                              frontier column per lane, or
  *                                              edges of 64 columns balanced

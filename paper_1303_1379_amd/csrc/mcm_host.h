@@ -57,6 +57,7 @@ struct Options {
     bool apsb = false;        // driver
     bool wr = true;           // bfs
     bool wr_late = true;      // WR root check beside the edge visit (wave mapping)
+    int endpoints = 2;        // WR path ends per root: 0 all reached, 1 the first only, 2 auto (1 for APsB)
     int mapping = 2;          // 0 thread, 1 wave, 2 auto
     int loop = 2;             // 0 device, 1 host, 2 auto
     bool validate = false;

@@ -40,7 +40,8 @@ enum Flags : uint32_t {
     F_LEVELS = 8u,    // record column levels (inspection mode)
     F_NOAUG = 16u,    // one BFS phase only, no Alternate/Fix (levels, cover)
     F_WAVE = 32u,     // wave-balanced edge mapping (else one column per lane)
-    F_WR_LATE = 64u   // WR root check with the edge visit, off the load chain (wave mapping)
+    F_WR_LATE = 64u,  // WR root check with the edge visit, off the load chain (wave mapping)
+    F_ENDPOINT = 128u // WR: one augmenting-path end per root (the first reached), the others released
 };
 
 // Device view of one graph plus its working state.

@@ -228,8 +228,14 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
     } else if (mate == -1) {
         if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | 0xFFFFFFFEull)) {
             g.pred[r] = col;
-            newend = true;
-            if (flags & F_WR) g.cdone[root] = ph;
+            if ((flags & F_WR) && (flags & F_ENDPOINT)) {
+                // the root's path ends at the first unmatched row it reached;
+                // a later one stays marked and FixMatching frees it
+                newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
+            } else {
+                newend = true;
+                if (flags & F_WR) g.cdone[root] = ph;
+            }
         }
     }
 }

@@ -24,10 +24,13 @@ DRIVER_COMBOS = [
     dict(driver="apsb", bfs="plain", mapping="thread", loop="device"),
     dict(driver="apfb", bfs="wr", mapping="wave", loop="host"),
     dict(driver="apsb", bfs="wr", mapping="thread", loop="host"),
+    dict(driver="apfb", bfs="wr", mapping="wave", loop="device", endpoints="one"),
+    dict(driver="apsb", bfs="wr", mapping="wave", loop="device", endpoints="all"),
+    dict(driver="apsb", bfs="wr", mapping="thread", loop="host", endpoints="one"),
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="late", small_max=256)
+                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto")
 
 
 @pytest.fixture(autouse=True)
