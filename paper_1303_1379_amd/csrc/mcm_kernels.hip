@@ -253,29 +253,45 @@ DEV void add_stat(uint64_t *stats, int idx, uint64_t v)
     if (__lane_id() == 0 && v) atomicAdd((unsigned long long *)&stats[idx * 16], (unsigned long long)v);
 }
 
-// Per-lane counters (stats=1), accumulated over a whole run and added to
-// the control block once at the end.
+// Statistics (stats=1) of one workgroup, kept in LDS so that no register
+// holds them through the run: a count is reduced over the wavefront and
+// added by its first lane (wavefront-uniform calls, all lanes active); the
+// timers (StatIdx S_T_*) are kept by thread 0.  Indices are StatIdx.
+constexpr int kAccN = 12;
+
 struct Acc {
-    uint64_t edges = 0, expanded = 0, claimed = 0, found = 0, alt = 0, fix = 0, roots = 0;
-    uint64_t t_expand = 0, t_flush = 0, t_barrier = 0, t_small = 0, t_augment = 0;
-    DEV void flush(uint64_t *stats, bool leader)
+    uint64_t *c;  // LDS [kAccN]
+    DEV void add(int i, uint64_t v) const
     {
-        add_stat(stats, S_EDGES, edges);
-        add_stat(stats, S_EXPANDED, expanded);
-        add_stat(stats, S_CLAIMED, claimed);
-        add_stat(stats, S_FOUND, found);
-        add_stat(stats, S_ALT, alt);
-        add_stat(stats, S_FIX, fix);
-        add_stat(stats, S_ROOTS, roots);
-        if (leader) {
-            stats[S_T_EXPAND * 16] += t_expand;
-            stats[S_T_FLUSH * 16] += t_flush;
-            stats[S_T_BARRIER * 16] += t_barrier;
-            stats[S_T_SMALL * 16] += t_small;
-            stats[S_T_AUGMENT * 16] += t_augment;
+        v = wave_sum(v);
+        if (__lane_id() == 0 && v) __hip_atomic_fetch_add(&c[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    DEV void tick(int i, uint64_t dt) const
+    {
+        if (threadIdx.x == 0) c[i] += dt;
+    }
+    // Adds the counts to the control block's counters (timers too if
+    // `timers`); every thread of the workgroup calls it.
+    DEV void flush(uint64_t *stats, bool timers) const
+    {
+        __syncthreads();
+        const int i = (int)threadIdx.x;
+        if (i < S_T_EXPAND) {
+            if (c[i]) atomicAdd((unsigned long long *)&stats[i * 16], (unsigned long long)c[i]);
+        } else if (i < kAccN && timers) {
+            stats[i * 16] += c[i];
         }
+        __syncthreads();
     }
 };
+
+// Zeroed counters; every thread of the workgroup calls it.
+DEV Acc make_acc(uint64_t *lds)
+{
+    if (threadIdx.x < (unsigned)kAccN) lds[threadIdx.x] = 0;
+    __syncthreads();
+    return Acc{lds};
+}
 
 // Expand frontier entries [0, n) of `fq`; wavefront `wave` of `nwaves`
 // takes batches of 64 entries.  WAVE: the edges of the 64 entries are dealt
@@ -339,8 +355,8 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
         }
         if (flags & F_STATS) {
             const bool live = !(late && rdone == ph);
-            acc.edges += live ? deg : 0;
-            acc.expanded += (live && deg > 0);
+            acc.add(S_EDGES, live ? (uint64_t)deg : 0u);
+            acc.add(S_EXPANDED, (live && deg > 0) ? 1u : 0u);
         }
         if (WAVE) {
             const int incl = wave_incl_scan(deg);
@@ -370,7 +386,7 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
                 push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
                 stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt, st.de);
                 any_end |= newend;
-                if (flags & F_STATS) { acc.claimed += newcol; acc.found += newend; }
+                if (flags & F_STATS) { acc.add(S_CLAIMED, newcol ? 1u : 0u); acc.add(S_FOUND, newend ? 1u : 0u); }
             }
         } else {
             const int maxdeg = wave_max(deg);
@@ -385,14 +401,14 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
                 push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
                 stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt, st.de);
                 any_end |= newend;
-                if (flags & F_STATS) { acc.claimed += newcol; acc.found += newend; }
+                if (flags & F_STATS) { acc.add(S_CLAIMED, newcol ? 1u : 0u); acc.add(S_FOUND, newend ? 1u : 0u); }
             }
         }
     }
     if ((flags & F_APSB) && __ballot(any_end) != 0 && lane == 0) atomicOr(io.found, 1u);
     const uint64_t t1 = (flags & F_STATS) ? wall_clock64() : 0;
     const uint32_t added = block_flush(st, io.nfq, io.ncnt, g.ends, io.ecnt, s_tmp);
-    if (flags & F_STATS) { acc.t_expand += t1 - t0; acc.t_flush += wall_clock64() - t1; }
+    if (flags & F_STATS) { acc.tick(S_T_EXPAND, t1 - t0); acc.tick(S_T_FLUSH, wall_clock64() - t1); }
     return added;
 }
 
@@ -418,7 +434,7 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
             }
             if (flags & F_LEVELS) g.clevel[c] = un ? 0 : -1;
         }
-        if (flags & F_STATS) acc.roots += p;
+        if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
         push_entry(p, e, o.split, st, g.fq0, cnt);
     }
     block_flush(st, g.fq0, cnt, g.ends, nullptr, s_tmp);
@@ -434,19 +450,24 @@ DEV void alternate(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nth
     int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);  // low word of rw[r] is rlo[2r]
     for (uint32_t i = tid; i < nends; i += nthreads) {
         int r = g.ends[i];
+        int c = ld_i<S>(&g.pred[r]);
         uint32_t guard = 0;
-        while (r != -1) {
-            const int c = ld_i<S>(&g.pred[r]);
+        for (;;) {
             const int r2 = ld_i<S>(&g.cmatch[c]);
-            if (r2 != -1 && ld_i<S>(&g.pred[r2]) == c) break;  // c already flipped by another walk
+            // pred[r2] is both the conflict check and the next step's column
+            // (pred does not change during Alternate): one load for the two
+            const int c2 = r2 != -1 ? ld_i<S>(&g.pred[r2]) : -1;
+            if (r2 != -1 && c2 == c) break;  // c already flipped by another walk
             st_i<S>(&g.cmatch[c], r);
             st_i<S>(&rlo[2 * (size_t)r], c);
-            r = r2;
             ++steps;
+            if (r2 == -1) break;             // reached the root
+            r = r2;
+            c = c2;
             if (++guard > (uint32_t)g.nc + 1u) { set_status(ctrl, kEInternal); break; }
         }
     }
-    acc.alt += steps;
+    if (flags & F_STATS) acc.add(S_ALT, steps);
 }
 
 // FixMatching: a row whose column points elsewhere lost a race and is
@@ -461,7 +482,7 @@ DEV void fix_matching(const DevGraph &g, uint32_t tid, uint32_t nthreads, uint32
         if (m == -1) continue;
         if (m < 0 || g.cmatch[m] != (int)r) { rlo[2 * (size_t)r] = -1; resets += (m >= 0); }
     }
-    acc.fix += resets;
+    if (flags & F_STATS) acc.add(S_FIX, resets);
 }
 
 // ---------------------------------------------------------------------
@@ -668,7 +689,7 @@ DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uin
 
 // The phase loop of Algorithm 1 over the whole grid (cooperative launch).
 template <bool WAVE>
-DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt &o, uint64_t *stats, Stage &st,
+DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt &o, uint64_t *stats, Acc &acc, Stage &st,
                   uint32_t *s_tmp, uint32_t *s_loc, int *s_ok, uint32_t *ph_out, uint32_t *lv_out, Grp gr)
 {
     const uint32_t flags = o.flags;
@@ -677,7 +698,6 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     const uint32_t tid = gr.b * blockDim.x + threadIdx.x, nthreads = gr.n * blockDim.x;
     const bool leader = gr.b == 0 && threadIdx.x == 0;
     const bool timing = (flags & F_STATS) != 0;
-    Acc acc;
     uint32_t epoch = 0, total_levels = 0, ph = 1;
     auto fc = [&](int i) { return line(ctrl, L_FCOUNT0 + i); };
     auto fd = [&](int i) { return line(ctrl, L_FOUND0 + i); };
@@ -696,14 +716,14 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         const uint64_t t0 = timing ? wall_clock64() : 0;
         const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr, active, o.idle_sleep, p, share, in_level,
                                      s_loc + 8, &s);
-        if (timing) acc.t_barrier += wall_clock64() - t0;
+        if (timing) acc.tick(S_T_BARRIER, wall_clock64() - t0);
         return ok;
     };
     auto sync_all = [&](const Pub &p) -> bool {
         const uint64_t t0 = timing ? wall_clock64() : 0;
         const bool ok =
             grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr, gr.n, o.idle_sleep, p, 0u, always, s_loc + 8, &s);
-        if (timing) acc.t_barrier += wall_clock64() - t0;
+        if (timing) acc.tick(S_T_BARRIER, wall_clock64() - t0);
         return ok;
     };
     const Pub none{0, 0, 0, nullptr, nullptr, false};
@@ -720,7 +740,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
                 if (gr.b == 0) {
                     const uint64_t t0 = timing ? wall_clock64() : 0;
                     const LvState r = small_levels<WAVE>(g, ctrl, o, ph, L, s.n, st, s_tmp, s_loc, acc, &total_levels);
-                    if (timing) acc.t_small += wall_clock64() - t0;
+                    if (timing) acc.tick(S_T_SMALL, wall_clock64() - t0);
                     p = Pub{r.L, r.n, r.stop, nullptr, nullptr, false};
                 }
                 if (!sync(1, p, 0u)) return false;
@@ -753,21 +773,20 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             *line(ctrl, L_NENDS) = 0;
         }
         if (!sync_all(none)) return false;
-        if (timing) acc.t_augment += wall_clock64() - ta;
+        if (timing) acc.tick(S_T_AUGMENT, wall_clock64() - ta);
     }
     if (leader) { *ph_out = ph; *lv_out = total_levels; }
-    if (timing) acc.flush(stats, leader);
+    if (timing) acc.flush(stats, gr.b == 0);
     return true;
 }
 
 // The phase loop of Algorithm 1 inside one workgroup (graph owned by it).
 template <bool WAVE>
-DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint64_t *stats, Stage &st, uint32_t *s_tmp,
+DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, Acc &acc, Stage &st, uint32_t *s_tmp,
                    uint32_t *s_loc, uint32_t *ph_out, uint32_t *lv_out)
 {
     const uint32_t flags = o.flags;
     const uint32_t wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    Acc acc;
     uint32_t total_levels = 0, ph = 1;
     for (;; ++ph) {
         if (ph > o.max_phases) { if (threadIdx.x == 0) set_status(ctrl, kEInternal); return false; }
@@ -797,10 +816,6 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint64_t 
         fix_matching(g, threadIdx.x, blockDim.x, flags, acc);
     }
     __syncthreads();
-    if (flags & F_STATS) {
-        acc.t_expand = acc.t_flush = 0;  // per-graph timings are not meaningful summed over blocks
-        acc.flush(stats, false);
-    }
     *ph_out = ph;
     *lv_out = total_levels;
     return true;
@@ -864,11 +879,13 @@ __global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl,
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_ok;
     __shared__ uint32_t s_loc[12];
+    __shared__ uint64_t s_acc[kAccN];
     Stage st = make_stage(smem);
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
+    Acc acc = make_acc(s_acc);
     uint32_t ph = 0, lv = 0;
-    if (run_grid<WAVE>(g, ctrl, bar, o, stats, st, s_tmp, s_loc, &s_ok, &ph, &lv, Grp{blockIdx.x, gridDim.x}) &&
+    if (run_grid<WAVE>(g, ctrl, bar, o, stats, acc, st, s_tmp, s_loc, &s_ok, &ph, &lv, Grp{blockIdx.x, gridDim.x}) &&
         blockIdx.x == 0 && threadIdx.x == 0) {
         *line(ctrl, L_PHASE) = ph;
         *line(ctrl, L_LEVELS) = lv;
@@ -927,6 +944,7 @@ __global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *desc
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_ok;
     __shared__ uint32_t s_loc[12];
+    __shared__ uint64_t s_acc[kAccN];
     const uint32_t gi = blockIdx.x / group;
     if (gi >= (uint32_t)ngraphs) return;  // whole block: never part of any barrier
     const Grp gr{blockIdx.x % group, group};
@@ -938,8 +956,9 @@ __global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *desc
     Stage st = make_stage(smem);
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
+    Acc acc = make_acc(s_acc);
     uint32_t ph = 0, lv = 0;
-    if (run_grid<WAVE>(g, ctrl, bar, o, stats, st, s_tmp, s_loc, &s_ok, &ph, &lv, gr) && gr.b == 0 &&
+    if (run_grid<WAVE>(g, ctrl, bar, o, stats, acc, st, s_tmp, s_loc, &s_ok, &ph, &lv, gr) && gr.b == 0 &&
         threadIdx.x == 0) {
         *line(ctrl, L_PHASE) = ph;
         *line(ctrl, L_LEVELS) = lv;
@@ -973,9 +992,10 @@ __global__ void k_init_roots(DevGraph g, uint32_t *ctrl, RunOpt o)
     Stage st = make_stage(smem);
     const uint32_t flags = o.flags;
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nwaves = gridDim.x * (blockDim.x >> 6);
-    Acc acc;
+    __shared__ uint64_t s_acc[kAccN];
+    Acc acc = make_acc(s_acc);
     init_roots(g, wave, nwaves, o, line(ctrl, L_FCOUNT0), st, stage_tmp(smem), acc);
-    if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false); }
+    if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
 }
 
 template <bool WAVE>
@@ -992,22 +1012,25 @@ __global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint
     const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
     LevelIO io{(L & 1) ? g.fq0 : g.fq1, line(ctrl, L_FCOUNT0 + (L + 1) % 3), line(ctrl, L_NENDS),
                line(ctrl, L_FOUND0 + L % 3)};
-    Acc acc;
+    __shared__ uint64_t s_acc[kAccN];
+    Acc acc = make_acc(s_acc);
     expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
-    if (flags & F_STATS) { acc.t_expand = acc.t_flush = 0; acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false); }
+    if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
 }
 
 __global__ void k_alternate(DevGraph g, uint32_t *ctrl, uint32_t flags)
 {
     const uint32_t ne = *line(ctrl, L_NENDS);
-    Acc acc;
+    __shared__ uint64_t s_acc[kAccN];
+    Acc acc = make_acc(s_acc);
     alternate<kAgent>(g, ne, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, flags, ctrl, acc);
     if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
 }
 
 __global__ void k_fix(DevGraph g, uint32_t *ctrl, uint32_t flags)
 {
-    Acc acc;
+    __shared__ uint64_t s_acc[kAccN];
+    Acc acc = make_acc(s_acc);
     fix_matching(g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, flags, acc);
     if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1076,6 +1099,8 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
     __shared__ uint32_t s_loc[12];
     __shared__ int32_t s_next;
     __shared__ uint32_t s_m;
+    __shared__ uint64_t s_acc[kAccN];
+    Acc acc = make_acc(s_acc);
     Stage st = make_stage(smem);
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
@@ -1110,7 +1135,7 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
         if (threadIdx.x == 0) s_m = 0;
         __syncthreads();
         uint32_t ph = 0, lv = 0;
-        const bool ok = (g.nc > 0 && g.nr > 0) ? run_block<WAVE>(g, ctrl, o, stats, st, s_tmp, s_loc, &ph, &lv) : true;
+        const bool ok = (g.nc > 0 && g.nr > 0) ? run_block<WAVE>(g, ctrl, o, acc, st, s_tmp, s_loc, &ph, &lv) : true;
         __syncthreads();
         uint32_t m = 0;
         for (int r = threadIdx.x; r < g.nr; r += blockDim.x) d.out_r[r] = (int32_t)(uint32_t)g.rw[r];
@@ -1125,6 +1150,7 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
         }
         __syncthreads();
     }
+    if (o.flags & F_STATS) acc.flush(stats, false);
 }
 
 // ---------------------------------------------------------------------
