@@ -38,6 +38,7 @@ WORKLOADS = {
               "removed, random row/column permutation (seed 3), int32 CSC, greedy initial matching",
     "uniform2000": "2000 x 2000 uniform random bipartite graph, 4 row draws per column (seed 1), duplicates "
                    "removed, int32 CSC, greedy initial matching",
+    "grid2048p": "grid2048 under a random row and column permutation (seed 7), int32 CSC, greedy initial matching",
 }
 
 
@@ -196,6 +197,35 @@ def bench_variants(names, reps):
     return rows
 
 
+def bench_phases(names, drivers=("apfb", "apsb")):
+    """Per-phase BFS levels and augmenting-path ends (the paper's figure of
+    levels per BFS iteration) for each workload and driver, GPUBFS-WR, from
+    the same greedy matching; plus the matching time of a run without stats."""
+    import numpy as np
+    import torch
+    from paper_1303_1379_amd import graphgen as gg, mcm
+    rows = []
+    for name in names:
+        g = gg.workload(name)
+        _, cm0, rm0 = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)
+        dg = mcm.to_device(g)
+        icm, irm = torch.from_numpy(cm0).cuda(), torch.from_numpy(rm0).cuda()
+        for drv in drivers:
+            mcm.set_option("driver", drv)
+            mcm.set_option("stats", 1)
+            card, _, _ = mcm.match(dg, icm, irm)
+            lv, en = mcm.last_phases()
+            mcm.set_option("stats", 0)
+            mcm.match(dg, icm, irm)
+            ms = mcm.last_stats()["kernel_ms"]
+            rows.append({"workload": name, "driver": drv, "card": card, "ms": round(ms, 3), "phases": int(len(lv)),
+                         "levels": int(lv.sum()), "levels_max": int(lv.max()) if len(lv) else 0,
+                         "levels_mean": round(float(lv.mean()), 1) if len(lv) else 0.0,
+                         "levels_per_phase": lv.tolist(), "ends_per_phase": en.tolist()})
+    mcm.set_option("driver", "apfb")
+    return rows
+
+
 def measured_copy_gbs(nbytes=1 << 30, reps=5):
     """Device copy bandwidth: one elementwise kernel reading and writing
     nbytes each, timed with events on torch's stream (the stream it runs on)."""
@@ -232,6 +262,9 @@ def main():
     ap.add_argument("--variants", default="",
                     help="instead of the bench line: the APFB/APsB x WR/plain x wave/thread grid on these "
                          "comma-separated workloads (one JSON line)")
+    ap.add_argument("--phases", default="",
+                    help="instead of the bench line: BFS levels and path ends per phase, APFB and APsB, on these "
+                         "comma-separated workloads (one JSON line)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of matching, stream this many bytes through one elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -254,6 +287,11 @@ def main():
             if w not in WORKLOADS:
                 ap.error(f"unknown workload {w}")
         print(json.dumps({"variants": bench_variants(names, max(args.steps, 1))}), flush=True)
+        return
+
+    if args.phases:
+        names = [w for w in args.phases.split(",") if w]
+        print(json.dumps({"phases": bench_phases(names)}), flush=True)
         return
 
     if args.copy_bytes:

@@ -312,6 +312,23 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
 int mcm_set_option(const char *key, const char *value);
 int mcm_get_option(const char *key, char *buf, int32_t len);
 
+/*
+ * mcm_last_phases -- the per-phase record of the last mcm_match call on this
+ * process that ran with option "stats" = "1" on the device-loop or
+ * host-loop path (graphs above the one-workgroup size): for phase i,
+ * levels[i] = BFS levels expanded and ends[i] = unmatched rows reached
+ * (augmenting-path ends; 0 in the last phase, whose complete BFS found
+ * none).  This is the per-iteration view the paper plots for its variants
+ * (section 4, the figure of BFS levels per iteration).
+ *
+ *   levels, ends   HOST [cap] arrays (may be NULL when cap == 0)
+ *   cap            entries to write at most (>= 0)
+ *
+ * Returns the number of phases recorded (at most 4096; it may exceed cap),
+ * 0 if the last call kept no record, or MCM_EINVAL.
+ */
+int64_t mcm_last_phases(int32_t *levels, int32_t *ends, int64_t cap);
+
 /* Counters of the last mcm_match / mcm_match_batched call on this process. */
 typedef struct {
     int64_t phases;          /* phases run, including the last one that found nothing */

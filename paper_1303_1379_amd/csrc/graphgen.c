@@ -371,6 +371,43 @@ int gg_batch_member(uint64_t seed, int64_t gidx, int32_t lo, int32_t hi, int32_t
 
 /* -------- helpers ---------------------------------------------------------- */
 /* CSR (row -> columns, columns ascending) of a CSC graph. */
+/* -------- random row and column permutation of a pattern ---------------- */
+/* The RCP transform: new row of old row r is pr[r], new column of old
+ * column c is pc[c], both drawn by Fisher-Yates from `seed` (rows first);
+ * rows sorted within each new column.  Matching sizes are invariant under
+ * it; the structure the BFS sees is not.                                  */
+int gg_permute(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind, uint64_t seed, gg_graph *out)
+{
+    if (!out || nc < 0 || nr < 0 || !colptr) return -1;
+    memset(out, 0, sizeof *out);
+    const int64_t nnz = colptr[nc];
+    int32_t *pr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nr > 0 ? nr : 1));
+    int32_t *pc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+    out->colptr = (int32_t *)calloc((size_t)nc + 1, sizeof(int32_t));
+    out->rowind = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!pr || !pc || !out->colptr || !out->rowind) { free(pr); free(pc); gg_free(out); return -2; }
+    gg_rng g = { gg_seed_mix(seed, 0x52435050ULL) };
+    for (int32_t i = 0; i < nr; ++i) pr[i] = i;
+    for (int32_t i = 0; i < nc; ++i) pc[i] = i;
+    for (int64_t i = (int64_t)nr - 1; i > 0; --i) { int64_t j = gg_below(gg_next(&g), (uint32_t)(i + 1)); int32_t t = pr[i]; pr[i] = pr[j]; pr[j] = t; }
+    for (int64_t i = (int64_t)nc - 1; i > 0; --i) { int64_t j = gg_below(gg_next(&g), (uint32_t)(i + 1)); int32_t t = pc[i]; pc[i] = pc[j]; pc[j] = t; }
+    for (int32_t c = 0; c < nc; ++c) out->colptr[pc[c] + 1] = colptr[c + 1] - colptr[c];
+    for (int32_t i = 0; i < nc; ++i) out->colptr[i + 1] += out->colptr[i];
+    #pragma omp parallel for schedule(dynamic, 4096)
+    for (int32_t c = 0; c < nc; ++c) {
+        int32_t *dst = out->rowind + out->colptr[pc[c]];
+        const int32_t b = colptr[c], e = colptr[c + 1];
+        for (int32_t j = b; j < e; ++j) dst[j - b] = pr[rowind[j]];
+        isort(dst, e - b);
+    }
+    out->nc = nc;
+    out->nr = nr;
+    out->nnz = nnz;
+    free(pr);
+    free(pc);
+    return 0;
+}
+
 int gg_transpose(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind,
                  int32_t *rowptr, int32_t *colind)
 {

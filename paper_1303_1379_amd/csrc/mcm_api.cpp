@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <vector>
 
 using namespace mcm;
 
@@ -54,6 +55,7 @@ Workspace &workspace(int dev) { return g_ws[dev]; }
 std::mutex &workspace_mutex() { return g_ws_mu; }
 mcm_stats g_stats;
 std::mutex g_stats_mu;
+std::vector<uint32_t> g_phases;  // per-phase (levels, ends) of the last stats run of mcm_match
 
 void free_dev(void *p)
 {
@@ -76,6 +78,9 @@ int64_t ensure_base(Workspace &w, int dev)
     HIPCHK(hipMalloc(&w.mctrl, (size_t)kMultiMax * L_NLINES * 128));
     HIPCHK(hipMalloc(&w.mbar, (size_t)kMultiMax * kMaxGridBlocks * 128));
     HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&w.h_ctrl), (size_t)L_NLINES * 128, hipHostMallocDefault));
+    HIPCHK(hipMalloc(&w.ptrace, sizeof(uint32_t) * 2 * kPhaseTrace));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&w.h_ptrace), sizeof(uint32_t) * 2 * kPhaseTrace,
+                         hipHostMallocDefault));
     HIPCHK(hipEventCreate(&w.ev0));
     HIPCHK(hipEventCreate(&w.ev1));
     return 0;
@@ -197,6 +202,8 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
         HIPCHK(launch_persistent(g, w.ctrl, w.bar, ro, wave, blocks, o.block, st));
         HIPCHK(hipEventRecord(w.ev1, st));
         HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+        if ((flags & F_STATS) && g.ptrace)
+            HIPCHK(hipMemcpyAsync(w.h_ptrace, g.ptrace, sizeof(uint32_t) * 2 * kPhaseTrace, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         return 0;
     }
@@ -207,7 +214,7 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
         HIPCHK(hipStreamSynchronize(st));
         return 0;
     };
-    uint32_t phases = 0, levels = 0;
+    uint32_t phases = 0, levels = 0, levels_before = 0;
     int64_t rc;
     HIPCHK(hipEventRecord(w.ev0, st));
     for (uint32_t ph = 1;; ++ph) {
@@ -225,8 +232,13 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
             n = *ctrl_line(hc, L_FCOUNT0 + ((L + 1) % 3));
             ++L;
         }
-        phases = ph;
         const uint32_t ne = *ctrl_line(hc, L_NENDS);
+        if ((flags & F_STATS) && ph <= (uint32_t)kPhaseTrace) {
+            w.h_ptrace[2 * (ph - 1)] = levels - levels_before;
+            w.h_ptrace[2 * (ph - 1) + 1] = ne;
+        }
+        levels_before = levels;
+        phases = ph;
         if (ne == 0 || (flags & F_NOAUG)) break;
         HIPCHK(launch_alternate(g, w.ctrl, ne, flags, st));
         HIPCHK(launch_fix(g, w.ctrl, flags, st));
@@ -259,6 +271,13 @@ uint32_t base_flags(const Options &o, int64_t nc, int64_t nnz_hint)
 int current_device(int *dev)
 {
     return hipGetDevice(dev) == hipSuccess ? 0 : -1;
+}
+
+void record_phases(const uint32_t *pairs, uint32_t phases)
+{
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    g_phases.clear();
+    if (pairs) g_phases.assign(pairs, pairs + 2 * (size_t)std::min<uint32_t>(phases, kPhaseTrace));
 }
 
 void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int loop, uint32_t flags,
@@ -510,6 +529,18 @@ int mcm_last_stats(mcm_stats *out)
     return MCM_OK;
 }
 
+int64_t mcm_last_phases(int32_t *levels, int32_t *ends, int64_t cap)
+{
+    if (cap < 0 || (cap > 0 && (!levels || !ends))) return fail(MCM_EINVAL, "NULL output or negative capacity");
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    const int64_t n = (int64_t)g_phases.size() / 2;
+    for (int64_t i = 0; i < std::min(n, cap); ++i) {
+        levels[i] = (int32_t)g_phases[2 * i];
+        ends[i] = (int32_t)g_phases[2 * i + 1];
+    }
+    return n;
+}
+
 int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind, int32_t *cmatch,
                             int32_t *rmatch)
 {
@@ -586,6 +617,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
         int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
         int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
         record_stats(w.h_ctrl, init_card, card, ms, loop, flags, w.info.clock_khz);
+        record_phases(nullptr, 0);  // the one-workgroup path keeps no per-phase record
         if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
         return card;
     }
@@ -603,6 +635,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     g.fq1 = w.fq + w.cap_q;
     g.ends = w.ends;
     g.clevel = nullptr;
+    g.ptrace = (flags & F_STATS) ? w.ptrace : nullptr;
     HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, w.bar, flags, st));
     if ((rc = run_graph(w, o, g, flags, st, &loop))) return rc;
     HIPCHK(launch_finish(g, out_rmatch, w.ctrl, st));
@@ -612,6 +645,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     const int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
     const int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
     record_stats(w.h_ctrl, init_card, card, ms, loop, flags, w.info.clock_khz);
+    record_phases((flags & F_STATS) ? w.h_ptrace : nullptr, *ctrl_line(w.h_ctrl, L_PHASE));
     if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
     return card;
 }

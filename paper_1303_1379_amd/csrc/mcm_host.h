@@ -104,6 +104,8 @@ struct Workspace {
     uint32_t *mbar = nullptr;    // its arrival lines
     int32_t *order = nullptr;
     int64_t *card = nullptr;
+    uint32_t *ptrace = nullptr;    // [2 * kPhaseTrace] per-phase record of a stats run
+    uint32_t *h_ptrace = nullptr;  // pinned copy
     uint32_t *h_ctrl = nullptr;  // pinned
     BatchDesc *h_desc = nullptr; // pinned
     int32_t *h_order = nullptr;  // pinned
@@ -126,6 +128,9 @@ uint32_t base_flags(const Options &o, int64_t nc, int64_t nnz_hint);
 int current_device(int *dev);
 void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int loop, uint32_t flags,
                   double clock_khz);
+// The per-phase record of the last stats run of mcm_match (pairs of BFS
+// levels and unmatched rows reached), or none.
+void record_phases(const uint32_t *pairs, uint32_t phases);
 
 }  // namespace host
 }  // namespace mcm

@@ -26,6 +26,7 @@ enum CtrlLine : int {
     L_NLINES = L_STAT0 + 12
 };
 constexpr int kLineWords = 32;        // 128 B / 4 B
+constexpr int kPhaseTrace = 4096;     // phases whose (levels, ends) a stats run records
 constexpr int kMaxGridBlocks = 2048;  // arrival flags of the grid barrier, one line each
 
 enum StatIdx : int {
@@ -56,6 +57,8 @@ struct DevGraph {
     int4 *fq0, *fq1;         // [nc]   frontier queues {col, root, beg, end}
     int32_t *ends;           // [nr]   unmatched rows reached this phase
     int32_t *clevel;         // [nc]   column levels (F_LEVELS) or null
+    uint32_t *ptrace = nullptr;  // [2 * kPhaseTrace] per phase: BFS levels, unmatched rows reached
+                                 // (recorded with F_STATS), or null
 };
 
 // Options of one run, passed by value to the kernels.

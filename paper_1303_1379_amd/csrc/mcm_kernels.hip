@@ -729,6 +729,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     const Pub none{0, 0, 0, nullptr, nullptr, false};
     for (;; ++ph) {
         if (ph > o.max_phases) { if (leader) set_status(ctrl, kEInternal); return false; }
+        const uint32_t lv0 = total_levels;
         init_roots(g, wave, nwaves, o, fc(0), st, s_tmp, acc);
         if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
         for (;;) {
@@ -763,6 +764,10 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
                 return false;
         }
         const uint32_t ne = ld_u<kAgent>(line(ctrl, L_NENDS));
+        if (leader && timing && g.ptrace && ph <= (uint32_t)kPhaseTrace) {
+            g.ptrace[2 * (ph - 1)] = total_levels - lv0;
+            g.ptrace[2 * (ph - 1) + 1] = ne;
+        }
         if (ne == 0 || (flags & F_NOAUG)) break;
         const uint64_t ta = timing ? wall_clock64() : 0;
         alternate<kAgent>(g, ne, tid, nthreads, flags, ctrl, acc);

@@ -62,8 +62,11 @@ def _load():
         lib.gg_seed_mix.restype = ctypes.c_uint64
         lib.gg_request_trace.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32] + [ctypes.c_void_p] * 5
+        lib.gg_permute.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                   P(_GG)]
         lib.gg_free.argtypes = [P(_GG)]
-        for f in ("gg_uniform", "gg_grid5", "gg_rmat", "gg_batch_member", "gg_transpose", "gg_request_trace"):
+        for f in ("gg_uniform", "gg_grid5", "gg_rmat", "gg_batch_member", "gg_transpose", "gg_request_trace",
+                  "gg_permute"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -161,6 +164,19 @@ def rmat(scale: int, nsamples: int, seed: int, a=0.57, b=0.19, c=0.19, n_limit: 
     return _take(g, f"rmat_s{scale}_m{nsamples}_seed{seed}{'_perm' if permute else ''}")
 
 
+def permute(g: Graph, seed: int) -> Graph:
+    """Random row and column permutation of g (the RCP transform; rows
+    sorted within columns).  |M| is invariant; the BFS structure is not."""
+    out = _GG()
+    cp = np.ascontiguousarray(g.colptr, dtype=np.int32)
+    ri = np.ascontiguousarray(g.rowind, dtype=np.int32)
+    if ri.size == 0:
+        ri = np.zeros(1, np.int32)
+    _check(_load().gg_permute(g.nc, g.nr, cp.ctypes.data, ri.ctypes.data, ctypes.c_uint64(seed), ctypes.byref(out)),
+           "permute")
+    return _take(out, f"{g.name}_rcp{seed}")
+
+
 def batch_member(seed: int, gidx: int, lo: int = 64, hi: int = 65536, dmin: int = 2, dmax: int = 12,
                  halfband: int = 5, empty_frac: float = 0.02) -> Graph:
     """Graph `gidx` of an uneven batch (even: uniform rows, odd: banded)."""
@@ -201,14 +217,18 @@ def workload(name: str) -> Graph:
                   emptied (seed 2).
     rmat23      : R-MAT scale 23, 16 * 2^23 samples, (.57,.19,.19,.05),
                   duplicates removed, random row/column permutation (seed 3).
-    Reduced-size variants for tests: grid<k>, rmat<scale>.
+    grid2048p   : grid2048 under a random row and column permutation (seed 7),
+                  the paper's RCP transform.
+    Reduced-size variants for tests: grid<k>, grid<k>p, rmat<scale>.
     """
     if name == "uniform2000":
         return uniform(2000, 2000, 4, 1)
     if name.startswith("grid"):
-        k = int(name[4:])
+        perm = name.endswith("p")
+        k = int(name[4:-1] if perm else name[4:])
         nd = int(math.floor(0.03 * k * k))
-        return grid5(k, nd, nd, 2)
+        g = grid5(k, nd, nd, 2)
+        return permute(g, 7) if perm else g
     if name.startswith("rmat"):
         s = int(name[4:])
         return rmat(s, 16 * (1 << s), 3, permute=True)

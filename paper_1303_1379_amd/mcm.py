@@ -63,7 +63,7 @@ EXPORTS = ["mcm_match", "mcm_match_batched", "mcm_konig_cover", "mcm_bfs_levels"
            "mcm_cheap_init", "mcm_batch_plan_create", "mcm_batch_plan_run", "mcm_batch_plan_info",
            "mcm_batch_plan_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
            "mcm_server_stats_get", "mcm_server_destroy", "mcm_set_option", "mcm_get_option", "mcm_last_stats",
-           "mcm_strerror", "mcm_version"]
+           "mcm_last_phases", "mcm_strerror", "mcm_version"]
 
 _lib = None
 
@@ -114,6 +114,8 @@ def lib():
     L.mcm_get_option.restype = ctypes.c_int
     L.mcm_last_stats.argtypes = [ctypes.POINTER(mcm_stats)]
     L.mcm_last_stats.restype = ctypes.c_int
+    L.mcm_last_phases.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    L.mcm_last_phases.restype = ctypes.c_int64
     L.mcm_strerror.argtypes = [i64]
     L.mcm_strerror.restype = ctypes.c_char_p
     L.mcm_version.argtypes = []
@@ -164,6 +166,16 @@ def last_stats() -> dict:
     s = mcm_stats()
     _check(lib().mcm_last_stats(ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in mcm_stats._fields_}
+
+
+def last_phases():
+    """(levels, ends) per phase of the last mcm_match run with stats=1 on the
+    device- or host-loop path: BFS levels expanded and unmatched rows reached."""
+    n = _check(lib().mcm_last_phases(None, None, 0))
+    lv = np.zeros(max(n, 1), np.int32)
+    en = np.zeros(max(n, 1), np.int32)
+    _check(lib().mcm_last_phases(lv.ctypes.data, en.ctypes.data, n))
+    return lv[:n], en[:n]
 
 
 def version() -> str:

@@ -325,3 +325,28 @@ def test_full_size_certified(name):
         nd = int(np.floor(0.03 * n))
         _, dc, dr = gg.grid5(2048, nd, nd, 2, return_masks=True)
         assert n - int((dc | dr).sum()) <= card <= n - nd
+
+
+@pytest.mark.parametrize("loop", ["device", "host"])
+@pytest.mark.parametrize("name,driver", [("grid256", "apfb"), ("grid256p", "apfb"), ("rmat14", "apsb")])
+def test_phase_record(name, driver, loop):
+    """The per-phase record of a stats run agrees with the run's own
+    counters: as many phases, levels summing to the level count, every phase
+    but the last reaching an unmatched row and the last (complete BFS)
+    reaching none, at least one end per augmentation; the permuted grid
+    reaches the oracle's |M| too."""
+    g = gg.workload(name)
+    ref = _oracle_card(g)
+    _set(wg_threshold=0, loop=loop, driver=driver, stats=1)
+    card, _, _ = _gpu(g, certify=False)
+    assert card == ref
+    st = mcm.last_stats()
+    lv, en = mcm.last_phases()
+    assert len(lv) == st["phases"] and int(lv.sum()) == st["levels"]
+    assert (en[:-1] > 0).all() and en[-1] == 0
+    init = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)[0]
+    assert int(en.sum()) >= card - init
+    # a run without stats keeps no record
+    _set(stats=0)
+    _gpu(g, certify=False)
+    assert len(mcm.last_phases()[0]) == 0
