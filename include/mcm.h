@@ -303,7 +303,7 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *   "autotune"  "0" (default) | "1"            batch plans time candidates
  *   "block", "blocks_per_cu", "wg_block", "wg_threshold", "small_max",
  *   "batch_min", "split", "timeout_s", "max_blocks", "level_entries",
- *   "idle_sleep", "wr_check", "multi_threshold", "multi_group"
+ *   "idle_sleep", "wr_check", "barrier", "multi_threshold", "multi_group"
  *                                              launch-shape details (see
  *                                              the host driver)
  * Return MCM_OK or MCM_EINVAL (unknown key or value).  mcm_get_option

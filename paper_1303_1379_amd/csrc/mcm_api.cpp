@@ -258,6 +258,7 @@ uint32_t base_flags(const Options &o, int64_t nc, int64_t nnz_hint)
     uint32_t f = 0;
     if (o.wr) f |= F_WR;
     if (o.wr_late) f |= F_WR_LATE;
+    if (o.bar_counter) f |= F_BAR_COUNTER;
     if (o.endpoints == 1 || (o.endpoints == 2 && o.apsb)) f |= F_ENDPOINT;
     if (o.apsb) f |= F_APSB;
     if (o.stats) f |= F_STATS;
@@ -459,6 +460,10 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "one") g_opt.endpoints = 1;
         else if (v == "auto") g_opt.endpoints = 2;
         else return (int)fail(MCM_EINVAL, "endpoints must be all, one or auto");
+    } else if (k == "barrier") {
+        if (v == "flags") g_opt.bar_counter = false;
+        else if (v == "counter") g_opt.bar_counter = true;
+        else return (int)fail(MCM_EINVAL, "barrier must be flags or counter");
     } else if (k == "wr_check") {
         if (v == "late") g_opt.wr_late = true;
         else if (v == "early") g_opt.wr_late = false;
@@ -511,6 +516,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "level_entries") v = std::to_string(o.level_entries);
     else if (k == "idle_sleep") v = std::to_string(o.idle_sleep);
     else if (k == "wr_check") v = o.wr_late ? "late" : "early";
+    else if (k == "barrier") v = o.bar_counter ? "counter" : "flags";
     else if (k == "endpoints") v = o.endpoints == 0 ? "all" : (o.endpoints == 1 ? "one" : "auto");
     else if (k == "multi_group") v = std::to_string(o.multi_group);
     else if (k == "batch_min") v = std::to_string(o.batch_min);

@@ -73,6 +73,7 @@ struct Options {
     int batch_min = 8;        // fewest frontier entries per wavefront batch
     int split = 64;           // heavier columns enter the frontier in pieces of this many edges (0 = off)
     int level_entries = 128;  // grid levels: one block per this many frontier entries (0 = all blocks)
+    bool bar_counter = true;  // grid barrier: last arrival of a counter releases (else flag lines)
     int idle_sleep = 8;       // barrier polls of blocks that sat a level out: s_sleep(1) count between
     int64_t multi_threshold = 1 << 15;  // batch members with nc + nr above this: multi-graph launches (0 = never)
     int multi_group = 0;      // blocks per graph in a multi-graph launch (0 = CUs / 4)

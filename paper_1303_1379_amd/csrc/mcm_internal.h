@@ -22,6 +22,8 @@ enum CtrlLine : int {
     L_LEVELS,          // BFS levels expanded, all phases
     L_CARD,            // |M| (64-bit)
     L_SMALL_LEVELS,    // levels expanded by single-workgroup runs (counter)
+    L_BAR_CNT0,        // arrival counters of the counter barrier (64-bit), even and odd epochs
+    L_BAR_CNT1,
     L_STAT0,           // stats counters (64-bit each, own lines)
     L_NLINES = L_STAT0 + 12
 };
@@ -42,7 +44,8 @@ enum Flags : uint32_t {
     F_NOAUG = 16u,    // one BFS phase only, no Alternate/Fix (levels, cover)
     F_WAVE = 32u,     // wave-balanced edge mapping (else one column per lane)
     F_WR_LATE = 64u,  // WR root check with the edge visit, off the load chain (wave mapping)
-    F_ENDPOINT = 128u // WR: one augmenting-path end per root (the first reached), the others released
+    F_ENDPOINT = 128u,  // WR: one augmenting-path end per root (the first reached), the others released
+    F_BAR_COUNTER = 256u  // grid barrier: the last arrival of a counter releases (else block 0 polls flags)
 };
 
 // Device view of one graph plus its working state.

@@ -525,16 +525,100 @@ struct Pub {
     bool sum;
 };
 
+// Wait (thread 0) until block 0 or the last arrival has released `epoch`
+// or a later one, and take the state it released; the acquire only where
+// `touches` says so.  Returns false on a status or the wait limit.
+template <class Touches>
+DEV bool wait_release(uint32_t *ctrl, const uint64_t *wa, const uint64_t *wb, uint32_t epoch, uint64_t timeout,
+                      bool arrived, uint32_t idle_sleep, Touches touches, uint32_t *s_st)
+{
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        const uint64_t a = __hip_atomic_load(wa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int32_t)((uint32_t)a - epoch) >= 0) {
+            // only a pair naming one epoch is taken: a stale B (or a newer
+            // one) sends the reader round again
+            const uint64_t w = __hip_atomic_load(wb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)w == (uint32_t)a) {
+                const LvState x{(uint32_t)(w >> 32) & 0x7fffffffu, (uint32_t)(a >> 32), (uint32_t)(w >> 63)};
+                if (touches(x)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                s_st[0] = x.L;
+                s_st[1] = x.n;
+                s_st[2] = x.stop;
+                s_st[3] = (uint32_t)a;
+                return true;
+            }
+            continue;  // the releaser moved on between the two loads: read both again
+        }
+        if (status_of(ctrl) != 0) return false;
+        if (wall_clock64() - t0 > timeout) { set_status(ctrl, kEInternal); return false; }
+        // a block that did not arrive polls less often: many of them
+        // polling one line slow every other access of the level
+        if (arrived) __builtin_amdgcn_s_sleep(1);
+        else for (uint32_t k = 0; k < idle_sleep; ++k) __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Release (thread 0): state B = {epoch, L | stop << 31} first, then
+// A = {epoch, n} with release order.
+DEV void release_state(uint64_t *wa, uint64_t *wb, uint32_t epoch, uint32_t L, uint32_t n, uint32_t stop,
+                       uint32_t *s_st)
+{
+    __hip_atomic_store(wb, ((uint64_t)(L | stop << 31) << 32) | epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(wa, ((uint64_t)n << 32) | epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    s_st[0] = L;
+    s_st[1] = n;
+    s_st[2] = stop;
+    s_st[3] = epoch;
+}
+
+// Two ways to close an epoch (option "barrier"):
+//  flags   -- every arriving block but 0 stores {epoch, share} in its own
+//             line; wave 0 of block 0 polls those lines, sums the shares
+//             and releases (no contended address; two hops: the arrival,
+//             then block 0's release);
+//  counter -- every arriving block adds {1 arrival, stop bit, share} to a
+//             64-bit counter of the epoch's parity (arrivals in bits 48..63,
+//             stop bits in 32..47, shares in 0..31); the add that completes
+//             the count returns the totals to the last block, which resets
+//             the counter for two epochs later and releases (one hop, one
+//             contended atomic per arriving block).
 template <class Touches>
 DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t timeout, int *s_ok, Grp gr,
-                      uint32_t active, uint32_t idle_sleep, const Pub &pub, uint32_t share, Touches touches,
-                      uint32_t *s_st, LvState *out)
+                      uint32_t active, uint32_t idle_sleep, bool counter, const Pub &pub, uint32_t share,
+                      Touches touches, uint32_t *s_st, LvState *out)
 {
     __syncthreads();
     ++epoch;
     uint64_t *wa = reinterpret_cast<uint64_t *>(line(ctrl, L_BAR_GEN));
     uint64_t *wb = reinterpret_cast<uint64_t *>(line(ctrl, L_BAR_GEN) + 16);
-    if (gr.b == 0) {
+    if (counter) {
+        if (threadIdx.x == 0) {
+            int ok = status_of(ctrl) == 0;
+            s_st[3] = epoch;
+            bool released = false;
+            if (ok && gr.b < active) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                uint64_t *cnt = reinterpret_cast<uint64_t *>(line(ctrl, (epoch & 1) ? L_BAR_CNT1 : L_BAR_CNT0));
+                const uint64_t mine = (1ull << 48) | ((uint64_t)(share >> 31) << 32) | (share & 0x7fffffffu);
+                const uint64_t tot = __hip_atomic_fetch_add(cnt, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + mine;
+                if ((uint32_t)(tot >> 48) == active) {
+                    __hip_atomic_store(cnt, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    uint32_t n = pub.n_ptr ? ld_u<kAgent>(pub.n_ptr) : pub.n;
+                    uint32_t stop = pub.stop_ptr ? (uint32_t)(ld_u<kAgent>(pub.stop_ptr) != 0) : pub.stop;
+                    if (pub.sum) {
+                        n = (uint32_t)(tot & 0xffffffffu);
+                        stop = ((tot >> 32) & 0xffffu) != 0 ? 1u : 0u;
+                    }
+                    release_state(wa, wb, epoch, pub.L, n, stop, s_st);
+                    released = true;
+                }
+            }
+            if (ok && !released) ok = wait_release(ctrl, wa, wb, epoch, timeout, gr.b < active, idle_sleep, touches, s_st);
+            *s_ok = ok;
+        }
+    } else if (gr.b == 0) {
         if (threadIdx.x < 64) {
             int ok = status_of(ctrl) == 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -567,15 +651,7 @@ DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t t
                     n += all_added;
                     stop |= any_ended ? 1u : 0u;
                 }
-                if (ok) {
-                    __hip_atomic_store(wb, ((uint64_t)(pub.L | stop << 31) << 32) | epoch, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(wa, ((uint64_t)n << 32) | epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                s_st[0] = pub.L;
-                s_st[1] = n;
-                s_st[2] = stop;
-                s_st[3] = epoch;
+                if (ok) release_state(wa, wb, epoch, pub.L, n, stop, s_st);
                 *s_ok = ok;
             }
         }
@@ -588,31 +664,7 @@ DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t t
                 __hip_atomic_store(reinterpret_cast<uint64_t *>(bar + (size_t)gr.b * kLineWords),
                                    ((uint64_t)share << 32) | epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            const uint64_t t0 = wall_clock64();
-            for (;;) {
-                const uint64_t a = __hip_atomic_load(wa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if ((int32_t)((uint32_t)a - epoch) >= 0) {
-                    // only a pair naming one epoch is taken: a stale B (or a
-                    // newer one) sends the reader round again
-                    const uint64_t w = __hip_atomic_load(wb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if ((uint32_t)w == (uint32_t)a) {
-                        const LvState x{(uint32_t)(w >> 32) & 0x7fffffffu, (uint32_t)(a >> 32), (uint32_t)(w >> 63)};
-                        if (touches(x)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                        s_st[0] = x.L;
-                        s_st[1] = x.n;
-                        s_st[2] = x.stop;
-                        s_st[3] = (uint32_t)a;
-                        break;
-                    }
-                    continue;  // block 0 moved on between the two loads: read both again
-                }
-                if (status_of(ctrl) != 0) { ok = 0; break; }
-                if (wall_clock64() - t0 > timeout) { set_status(ctrl, kEInternal); ok = 0; break; }
-                // a block that did not arrive polls less often: many of them
-                // polling one line slow every other access of the level
-                if (gr.b < active) __builtin_amdgcn_s_sleep(1);
-                else for (uint32_t k = 0; k < idle_sleep; ++k) __builtin_amdgcn_s_sleep(1);
-            }
+            ok = wait_release(ctrl, wa, wb, epoch, timeout, gr.b < active, idle_sleep, touches, s_st);
         }
         *s_ok = ok;
     }
@@ -712,17 +764,18 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         return gr.b < level_blocks(x.n, o.level_entries, gr.n);
     };
     auto always = [](const LvState &) -> bool { return true; };
+    const bool counter = (flags & F_BAR_COUNTER) != 0;
     auto sync = [&](uint32_t active, const Pub &p, uint32_t share) -> bool {
         const uint64_t t0 = timing ? wall_clock64() : 0;
-        const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr, active, o.idle_sleep, p, share, in_level,
-                                     s_loc + 8, &s);
+        const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr, active, o.idle_sleep, counter, p, share,
+                                     in_level, s_loc + 8, &s);
         if (timing) acc.tick(S_T_BARRIER, wall_clock64() - t0);
         return ok;
     };
     auto sync_all = [&](const Pub &p) -> bool {
         const uint64_t t0 = timing ? wall_clock64() : 0;
-        const bool ok =
-            grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr, gr.n, o.idle_sleep, p, 0u, always, s_loc + 8, &s);
+        const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr, gr.n, o.idle_sleep, counter, p, 0u, always,
+                                     s_loc + 8, &s);
         if (timing) acc.tick(S_T_BARRIER, wall_clock64() - t0);
         return ok;
     };

@@ -30,7 +30,7 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto")
+                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto", barrier="counter")
 
 
 @pytest.fixture(autouse=True)
@@ -204,7 +204,10 @@ ELASTIC = [dict(level_entries=0, idle_sleep=1, small_max=256, driver="apfb", wr_
            dict(level_entries=1, idle_sleep=0, small_max=0, driver="apfb", wr_check="late"),
            dict(level_entries=64, idle_sleep=1, small_max=0, driver="apsb", wr_check="early"),
            dict(level_entries=4096, idle_sleep=64, small_max=256, driver="apsb", wr_check="late"),
-           dict(level_entries=4096, idle_sleep=8, small_max=0, driver="apfb", wr_check="early")]
+           dict(level_entries=4096, idle_sleep=8, small_max=0, driver="apfb", wr_check="early"),
+           dict(level_entries=1, idle_sleep=0, small_max=0, driver="apfb", wr_check="late", barrier="flags"),
+           dict(level_entries=128, idle_sleep=8, small_max=256, driver="apsb", wr_check="late", barrier="counter"),
+           dict(level_entries=0, idle_sleep=1, small_max=0, driver="apsb", wr_check="early", barrier="flags")]
 
 
 @pytest.mark.parametrize("combo", ELASTIC, ids=lambda c: "-".join(str(v) for v in c.values()))
