@@ -100,10 +100,10 @@ typedef struct {
  * device launch (one persistent kernel drains a work queue of graphs,
  * largest first; each graph is matched by one workgroup with the same
  * phases as mcm_match).  Members with ncols + nrows above the option
- * "multi_threshold" (default 2^15) are matched instead by a group of
- * "multi_group" blocks each (default: a quarter of the CUs), several
- * graphs per cooperative launch, after the workgroup kernel on the same
- * stream.  Defined to equal calling mcm_match on each graph: the per-graph
+ * "multi_threshold" (default 2^15) are matched instead, after the
+ * workgroup kernel on the same stream, by one cooperative launch whose
+ * groups of "multi_group" blocks (default: an eighth of the CUs) take them
+ * from a queue.  Defined to equal calling mcm_match on each graph: the per-graph
  * cardinalities are identical.
  *
  *   ngraphs            >= 0
@@ -181,9 +181,9 @@ int64_t mcm_cheap_init(int32_t ncols, int32_t nrows, const int32_t *colptr, cons
  * the queue until memory returns.  A worker thread copies admitted inputs
  * to the device on a copy stream and keeps launching the batched matcher
  * over every admitted request whose inputs have arrived, while new requests
- * are admitted and copied; requests with nc + nr above 2^15 are matched
- * by a group of blocks each (a quarter of the CUs), up to eight such
- * requests per cooperative launch.  Every request starts from the device cheap matching and ends
+ * are admitted and copied; requests with nc + nr above 2^15 go, up to 64
+ * per launch, to one cooperative launch whose groups of blocks (an eighth
+ * of the CUs each) take them from a queue.  Every request starts from the device cheap matching and ends
  * with a maximum matching of its graph, copied back into the caller's
  * arrays; its memory is then released.
  *

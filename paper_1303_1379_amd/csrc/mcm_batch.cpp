@@ -225,18 +225,19 @@ int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs, const int32_
     ro.batch_min = (uint32_t)cfg.batch_min;
     HIPCHK(prepare_match_wg(cfg.block));
     const int blocks = batch_blocks(w.info, cfg.wave, cfg.block, std::max(nsmall, 1));
-    // multi-graph launch shape: `group` blocks per graph, `per_launch` graphs
-    // co-resident (a cooperative launch must fit the device at once)
+    // multi-graph launch shape: `ngroups` groups of `group` blocks, all
+    // co-resident (a cooperative launch must fit the device at once), take
+    // the large members from a queue
     const bool mwave = (flags & F_WAVE) != 0;
-    int group = 1, per_launch = 1;
+    int group = 1, ngroups = 1;
     if (nlarge) {
         int occ = 0;
         HIPCHK(multi_occupancy(mwave, o.block, &occ));
         const int resident = w.info.ncu * std::max(occ, 0);
         if (resident < 1) return fail(MCM_EHIP, "multi-graph kernel does not fit a CU with block %d", o.block);
-        group = o.multi_group > 0 ? o.multi_group : std::max(1, w.info.ncu / 4);
+        group = o.multi_group > 0 ? o.multi_group : std::max(1, w.info.ncu / 8);
         group = std::min(group, std::min(resident, kMaxGridBlocks));
-        per_launch = std::max(1, std::min(kMultiMax, resident / group));
+        ngroups = std::max(1, std::min(std::min(kMultiMax, resident / group), (int)nlarge));
     }
     RunOpt mro = run_opt(o, flags, std::max<int64_t>(ex.col_ext, 1), w.info);
     mro.split = 0;  // same queue slices as above
@@ -246,11 +247,9 @@ int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs, const int32_
     HIPCHK(hipEventRecord(w.ev0, st));
     if (nsmall)
         HIPCHK(launch_match_wg(w.desc, w.order + nlarge, nsmall, w.card, w.ctrl, ro, cfg.wave, blocks, cfg.block, st));
-    for (int32_t j = 0; j < nlarge; j += per_launch) {
-        const int32_t n = std::min(per_launch, nlarge - j);
-        HIPCHK(launch_multi(w.desc + ngraphs + j, n, group, w.mctrl, w.mbar, w.card + ngraphs + j, mro, mwave, o.block,
-                            st));
-    }
+    if (nlarge)
+        HIPCHK(launch_multi(w.desc + ngraphs, nlarge, group, ngroups, w.mctrl, w.mbar, w.card + ngraphs, mro, mwave,
+                            o.block, st));
     HIPCHK(hipEventRecord(w.ev1, st));
     HIPCHK(hipMemcpyAsync(w.h_card, w.card, sizeof(int64_t) * (ngraphs + nlarge), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));

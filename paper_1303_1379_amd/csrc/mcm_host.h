@@ -34,9 +34,9 @@ hipError_t prepare_match_wg(int block);
 hipError_t match_wg_occupancy(bool wave, int block, int *per_cu);
 hipError_t launch_cheap_init(const BatchDesc *descs, int32_t ngraphs, hipStream_t st);
 hipError_t multi_occupancy(bool wave, int block, int *per_cu);
-constexpr int kMultiMax = 8;  // graphs per multi-graph launch (upper bound)
-hipError_t launch_multi(const BatchDesc *descs, int32_t ngraphs, int group, uint32_t *ctrls, uint32_t *bars,
-                        int64_t *card, const RunOpt &o, bool wave, int block, hipStream_t st);
+constexpr int kMultiMax = 16;  // block groups (control blocks) of a multi-graph launch, upper bound
+hipError_t launch_multi(const BatchDesc *descs, int32_t ngraphs, int group, int ngroups, uint32_t *ctrls,
+                        uint32_t *bars, int64_t *card, const RunOpt &o, bool wave, int block, hipStream_t st);
 
 namespace host {
 
@@ -76,7 +76,7 @@ struct Options {
     bool bar_counter = true;  // grid barrier: last arrival of a counter releases (else flag lines)
     int idle_sleep = 8;       // barrier polls of blocks that sat a level out: s_sleep(1) count between
     int64_t multi_threshold = 1 << 15;  // batch members with nc + nr above this: multi-graph launches (0 = never)
-    int multi_group = 0;      // blocks per graph in a multi-graph launch (0 = CUs / 4)
+    int multi_group = 0;      // blocks per group of a multi-graph launch (0 = CUs / 8)
     double timeout_s = 20.0;  // device barrier wait limit
 };
 Options opts();

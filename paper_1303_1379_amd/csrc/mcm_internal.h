@@ -24,6 +24,7 @@ enum CtrlLine : int {
     L_SMALL_LEVELS,    // levels expanded by single-workgroup runs (counter)
     L_BAR_CNT0,        // arrival counters of the counter barrier (64-bit), even and odd epochs
     L_BAR_CNT1,
+    L_TAKE,            // multi-graph launch: the graph a group's block 0 took from the queue
     L_STAT0,           // stats counters (64-bit each, own lines)
     L_NLINES = L_STAT0 + 12
 };

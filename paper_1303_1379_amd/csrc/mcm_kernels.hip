@@ -282,6 +282,8 @@ struct Acc {
             stats[i * 16] += c[i];
         }
         __syncthreads();
+        if (i < kAccN) c[i] = 0;
+        __syncthreads();
     }
 };
 
@@ -742,7 +744,8 @@ DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uin
 // The phase loop of Algorithm 1 over the whole grid (cooperative launch).
 template <bool WAVE>
 DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt &o, uint64_t *stats, Acc &acc, Stage &st,
-                  uint32_t *s_tmp, uint32_t *s_loc, int *s_ok, uint32_t *ph_out, uint32_t *lv_out, Grp gr)
+                  uint32_t *s_tmp, uint32_t *s_loc, int *s_ok, uint32_t *ph_out, uint32_t *lv_out, Grp gr,
+                  uint32_t &epoch)
 {
     const uint32_t flags = o.flags;
     const uint32_t wave = gr.b * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -750,7 +753,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     const uint32_t tid = gr.b * blockDim.x + threadIdx.x, nthreads = gr.n * blockDim.x;
     const bool leader = gr.b == 0 && threadIdx.x == 0;
     const bool timing = (flags & F_STATS) != 0;
-    uint32_t epoch = 0, total_levels = 0, ph = 1;
+    uint32_t total_levels = 0, ph = 1;
     auto fc = [&](int i) { return line(ctrl, L_FCOUNT0 + i); };
     auto fd = [&](int i) { return line(ctrl, L_FOUND0 + i); };
     // grid barrier (`active` blocks arrive; block 0 releases the loop state
@@ -942,8 +945,9 @@ __global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl,
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
     Acc acc = make_acc(s_acc);
-    uint32_t ph = 0, lv = 0;
-    if (run_grid<WAVE>(g, ctrl, bar, o, stats, acc, st, s_tmp, s_loc, &s_ok, &ph, &lv, Grp{blockIdx.x, gridDim.x}) &&
+    uint32_t ph = 0, lv = 0, epoch = 0;
+    if (run_grid<WAVE>(g, ctrl, bar, o, stats, acc, st, s_tmp, s_loc, &s_ok, &ph, &lv, Grp{blockIdx.x, gridDim.x},
+                       epoch) &&
         blockIdx.x == 0 && threadIdx.x == 0) {
         *line(ctrl, L_PHASE) = ph;
         *line(ctrl, L_LEVELS) = lv;
@@ -974,73 +978,111 @@ DEV DevGraph graph_of(const BatchDesc &d)
     return g;
 }
 
-// blockIdx.y = graph: working state from the initial matching, |M| slot and
-// the graph's control block and arrival lines reset.
-__global__ void k_setup_multi(const BatchDesc *descs, int32_t ngraphs, uint32_t *ctrls, uint32_t *bars,
-                              uint32_t bar_lines, int64_t *card)
+// Completion mark of a graph of a multi-graph launch, in its card slot:
+// the counts that k_finish_multi adds on top keep every reader seeing it.
+constexpr int64_t kGraphDone = (int64_t)1 << 62;
+
+// Before a multi-graph launch.  blockIdx.y = graph: working state from the
+// initial matching, and card[graph] = kEInternal, which the group that
+// completes the graph replaces by kGraphDone (k_finish_multi then adds |M|
+// to it; a graph left unprocessed after a watchdog keeps the error).  The groups'
+// control blocks and arrival lines, and the graph queue in the first
+// control block, start at zero.
+__global__ void k_setup_multi(const BatchDesc *descs, int32_t ngraphs, int32_t ngroups, uint32_t *ctrls,
+                              uint32_t *bars, uint32_t bar_lines, int64_t *card)
 {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
     for (int32_t gi = blockIdx.y; gi < ngraphs; gi += gridDim.y) {
         const BatchDesc d = descs[gi];
-        const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
         for (uint32_t c = tid; c < (uint32_t)d.nc; c += nt) {
             d.out_c[c] = d.init_c ? d.init_c[c] : -1;
             d.cdone[c] = 0;
         }
         for (uint32_t r = tid; r < (uint32_t)d.nr; r += nt) d.rw[r] = (uint64_t)(uint32_t)(d.init_r ? d.init_r[r] : -1);
-        uint32_t *ctrl = ctrls + (size_t)gi * L_NLINES * kLineWords;
-        uint32_t *bar = bars + (size_t)gi * bar_lines * kLineWords;
-        for (uint32_t i = tid; i < (uint32_t)(L_NLINES * kLineWords); i += nt) ctrl[i] = 0;
-        for (uint32_t i = tid; i < bar_lines * (uint32_t)kLineWords; i += nt) bar[i] = 0;
-        if (tid == 0) card[gi] = 0;
+        if (tid == 0) card[gi] = kEInternal;
+    }
+    if (blockIdx.y == 0) {
+        const uint32_t nctrl = (uint32_t)ngroups * L_NLINES * kLineWords, nbar = (uint32_t)ngroups * bar_lines * kLineWords;
+        for (uint32_t i = tid; i < nctrl; i += nt) ctrls[i] = 0;
+        for (uint32_t i = tid; i < nbar; i += nt) bars[i] = 0;
     }
 }
 
+// Many large graphs in one cooperative launch: the blocks form groups of
+// `group` blocks (own control block and arrival lines each), and every
+// group takes graph after graph from a queue (the L_QUEUE line of the
+// first control block) and runs the phase loop of k_persistent on it with
+// a barrier of its own, until the queue is empty.  Block 0 of a group takes
+// the next index and the group learns it through a barrier that releases
+// it as the frontier size.
 template <bool WAVE>
 __global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *descs, int32_t ngraphs, uint32_t group,
-                                                           uint32_t *ctrls, uint32_t *bars, RunOpt o)
+                                                           uint32_t *ctrls, uint32_t *bars, int64_t *card, RunOpt o)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_ok;
     __shared__ uint32_t s_loc[12];
     __shared__ uint64_t s_acc[kAccN];
-    const uint32_t gi = blockIdx.x / group;
-    if (gi >= (uint32_t)ngraphs) return;  // whole block: never part of any barrier
+    const uint32_t q = blockIdx.x / group;
     const Grp gr{blockIdx.x % group, group};
-    const BatchDesc d = descs[gi];
-    if (d.nc == 0 || d.nr == 0) return;   // whole group
-    DevGraph g = graph_of(d);
-    uint32_t *ctrl = ctrls + (size_t)gi * L_NLINES * kLineWords;
-    uint32_t *bar = bars + (size_t)gi * group * kLineWords;
+    uint32_t *ctrl = ctrls + (size_t)q * L_NLINES * kLineWords;
+    uint32_t *bar = bars + (size_t)q * group * kLineWords;
+    uint32_t *queue = line(ctrls, L_QUEUE);
     Stage st = make_stage(smem);
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
     Acc acc = make_acc(s_acc);
-    uint32_t ph = 0, lv = 0;
-    if (run_grid<WAVE>(g, ctrl, bar, o, stats, acc, st, s_tmp, s_loc, &s_ok, &ph, &lv, gr) && gr.b == 0 &&
-        threadIdx.x == 0) {
-        *line(ctrl, L_PHASE) = ph;
-        *line(ctrl, L_LEVELS) = lv;
+    const bool leader = gr.b == 0 && threadIdx.x == 0;
+    auto always = [](const LvState &) -> bool { return true; };
+    const bool counter = (o.flags & F_BAR_COUNTER) != 0;
+    uint32_t epoch = 0;
+    for (;;) {
+        if (leader) {
+            // the previous graph left its level counters behind
+            for (int i = 0; i < 3; ++i) { *line(ctrl, L_FCOUNT0 + i) = 0; *line(ctrl, L_FOUND0 + i) = 0; }
+            *line(ctrl, L_NENDS) = 0;
+            // whichever block releases the barrier reads the index from here
+            *line(ctrl, L_TAKE) = atomicAdd(queue, 1u);
+        }
+        LvState x;
+        if (!grid_barrier(ctrl, bar, epoch, o.timeout, &s_ok, gr, group, o.idle_sleep, counter,
+                          Pub{0, 0, 0, line(ctrl, L_TAKE), nullptr, false}, 0u, always, s_loc + 8, &x))
+            return;
+        const uint32_t gi = x.n;
+        if (gi >= (uint32_t)ngraphs) return;  // the whole group: the queue is drained
+        const BatchDesc d = descs[gi];
+        bool ok = true;
+        if (d.nc > 0 && d.nr > 0) {
+            DevGraph g = graph_of(d);
+            uint32_t ph = 0, lv = 0;
+            ok = run_grid<WAVE>(g, ctrl, bar, o, stats, acc, st, s_tmp, s_loc, &s_ok, &ph, &lv, gr, epoch);
+        }
+        if (!ok) return;                      // watchdog: this graph and the group stop
+        if (leader) card[gi] = kGraphDone;    // k_finish_multi counts |M| on top
     }
 }
 
-// blockIdx.y = graph: unpack rmatch, |M| = #{c : cmatch[c] >= 0} into
-// card[graph]; a graph whose group hit a watchdog gets the status instead.
-__global__ void k_finish_multi(const BatchDesc *descs, int32_t ngraphs, uint32_t *ctrls, int64_t *card)
+// blockIdx.y = graph: unpack rmatch and add |M| = #{c : cmatch[c] >= 0}
+// to card[graph] for every graph a group completed; the others keep the
+// error.  k_card_done then removes the completion mark.
+__global__ void k_finish_multi(const BatchDesc *descs, int32_t ngraphs, int64_t *card)
 {
     for (int32_t gi = blockIdx.y; gi < ngraphs; gi += gridDim.y) {
         const BatchDesc d = descs[gi];
-        const int32_t status = *(const int32_t *)line(ctrls + (size_t)gi * L_NLINES * kLineWords, L_STATUS);
+        if (card[gi] < kGraphDone) continue;  // not completed: the error stays
         const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
-        if (status != 0) {
-            if (tid == 0) card[gi] = status;
-            continue;
-        }
         for (uint32_t r = tid; r < (uint32_t)d.nr; r += nt) d.out_r[r] = (int32_t)(uint32_t)d.rw[r];
         uint64_t m = 0;
         for (uint32_t c = tid; c < (uint32_t)d.nc; c += nt) m += (d.out_c[c] >= 0);
         m = wave_sum(m);
         if (__lane_id() == 0 && m) atomicAdd((unsigned long long *)&card[gi], (unsigned long long)m);
     }
+}
+
+__global__ void k_card_done(int32_t ngraphs, int64_t *card)
+{
+    const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi < ngraphs && card[gi] >= kGraphDone) card[gi] -= kGraphDone;
 }
 
 // Host-driven steps (one launch each).
@@ -1414,26 +1456,34 @@ hipError_t multi_occupancy(bool wave, int block, int *per_cu)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, multi_fn(wave), block, lds);
 }
 
-// setup -> cooperative multi-graph launch (ngraphs groups of `group` blocks)
-// -> finish; card[ngraphs] receives |M_g|.  ctrls: ngraphs control blocks,
-// bars: ngraphs * group arrival lines.
-hipError_t launch_multi(const BatchDesc *descs, int32_t ngraphs, int group, uint32_t *ctrls, uint32_t *bars,
-                        int64_t *card, const RunOpt &o, bool wave, int block, hipStream_t st)
+// setup -> cooperative launch of ngroups groups of `group` blocks that take
+// the ngraphs graphs from a queue -> finish; card[ngraphs] receives |M_g|
+// (or kEInternal for a graph a watchdog left undone).  ctrls: ngroups
+// control blocks; bars: ngroups * group arrival lines.
+hipError_t launch_multi(const BatchDesc *descs, int32_t ngraphs, int group, int ngroups, uint32_t *ctrls,
+                        uint32_t *bars, int64_t *card, const RunOpt &o, bool wave, int block, hipStream_t st)
 {
+    if (ngraphs <= 0) return hipSuccess;
+    if (ngroups < 1 || group < 1) return hipErrorInvalidValue;
     const dim3 g2(256, (unsigned)(ngraphs < 65535 ? ngraphs : 65535));
-    hipLaunchKernelGGL(k_setup_multi, g2, dim3(256), 0, st, descs, ngraphs, ctrls, bars, (uint32_t)group, card);
+    hipLaunchKernelGGL(k_setup_multi, g2, dim3(256), 0, st, descs, ngraphs, ngroups, ctrls, bars, (uint32_t)group,
+                       card);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const BatchDesc *dd = descs;
     int32_t ng = ngraphs;
     uint32_t gp = (uint32_t)group;
     uint32_t *cc = ctrls, *bb = bars;
+    int64_t *cd = card;
     RunOpt oo = o;
-    void *args[] = {&dd, &ng, &gp, &cc, &bb, &oo};
-    e = hipLaunchCooperativeKernel(multi_fn(wave), dim3((unsigned)(ngraphs * group)), dim3(block), args,
+    void *args[] = {&dd, &ng, &gp, &cc, &bb, &cd, &oo};
+    e = hipLaunchCooperativeKernel(multi_fn(wave), dim3((unsigned)(ngroups * group)), dim3(block), args,
                                    (unsigned)stage_lds_bytes(block / 64), st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_finish_multi, g2, dim3(256), 0, st, descs, ngraphs, ctrls, card);
+    hipLaunchKernelGGL(k_finish_multi, g2, dim3(256), 0, st, descs, ngraphs, card);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_card_done, dim3((unsigned)((ngraphs + 255) / 256)), dim3(256), 0, st, ngraphs, card);
     return hipGetLastError();
 }
 

@@ -96,6 +96,8 @@ class Arena {
 
 enum ReqState { Q_PENDING, Q_COPYING, Q_READY, Q_RUNNING, Q_DONE };
 
+constexpr int kMultiGraphs = 64;  // large requests per multi-graph launch, at most
+
 struct Request {
     int64_t ticket = 0;
     int32_t nc = 0, nr = 0;
@@ -137,7 +139,8 @@ struct mcm_server {
     int32_t max_batch = 1024;
     int64_t big_threshold = 1 << 15;  // nc + nr above which a request joins a multi-graph launch
     int group = 64;                   // blocks per large request in a multi-graph launch
-    int multi_max = 4;                // large requests per multi-graph launch
+    int multi_max = 4;                // large requests per multi-graph launch (kMultiGraphs)
+    int ngroups = 1;                  // block groups of a multi-graph launch (they take requests from a queue)
     std::deque<Request *> big_ready;  // large requests waiting for a launch
     Arena arena;
     hipStream_t compute = nullptr, copy = nullptr;
@@ -280,7 +283,8 @@ int64_t launch_batch(mcm_server *s, Slot &slot, std::vector<Request *> &reqs)
     return 0;
 }
 
-// Up to multi_max large requests in one cooperative launch, `group` blocks each.
+// Up to multi_max large requests in one cooperative launch: ngroups groups
+// of `group` blocks take them from a queue.
 int64_t launch_multi_reqs(mcm_server *s, Slot &slot, std::vector<Request *> &reqs)
 {
     const int32_t n = (int32_t)reqs.size();
@@ -289,10 +293,12 @@ int64_t launch_multi_reqs(mcm_server *s, Slot &slot, std::vector<Request *> &req
     HIPCHK(launch_cheap_init(slot.d_desc, n, s->compute));
     const uint32_t flags = base_flags(s->opt, 0, 0) & ~(uint32_t)F_STATS;
     const RunOpt ro = run_opt(s->opt, flags, 1 << 30, s->info);
-    HIPCHK(launch_multi(slot.d_desc, n, s->group, slot.d_ctrl, slot.d_bar, slot.d_card, ro, (flags & F_WAVE) != 0,
-                        s->opt.block, s->compute));
+    const int ngroups = std::min(n, s->ngroups);
+    HIPCHK(launch_multi(slot.d_desc, n, s->group, ngroups, slot.d_ctrl, slot.d_bar, slot.d_card, ro,
+                        (flags & F_WAVE) != 0, s->opt.block, s->compute));
     HIPCHK(hipMemcpyAsync(slot.h_card, slot.d_card, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s->compute));
-    HIPCHK(hipMemcpyAsync(slot.h_ctrl, slot.d_ctrl, (size_t)n * L_NLINES * 128, hipMemcpyDeviceToHost, s->compute));
+    HIPCHK(hipMemcpyAsync(slot.h_ctrl, slot.d_ctrl, (size_t)ngroups * L_NLINES * 128, hipMemcpyDeviceToHost,
+                          s->compute));
     HIPCHK(hipEventRecord(slot.done, s->compute));
     const double t = s->now_ms();
     for (int32_t i = 0; i < n; ++i) {
@@ -307,7 +313,7 @@ int64_t launch_multi_reqs(mcm_server *s, Slot &slot, std::vector<Request *> &req
         if ((rc = start_copy_back(s, r, slot.done))) return rc;
     }
     slot.busy = true;
-    slot.ngroups = n;
+    slot.ngroups = ngroups;
     slot.reqs = reqs;
     s->st.launches_grid += 1;
     return 0;
@@ -436,16 +442,18 @@ int64_t mcm_server_create(int64_t hbm_budget_bytes, int32_t max_batch, mcm_serve
     if (hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(MCM_EHIP, "stream creation failed"));
-    // large requests: `group` blocks each (one persistent block per CU), as many per launch as the
-    // device holds at once
-    s->group = std::max(1, s->info.ncu / 4);
+    // large requests: groups of `group` blocks (one persistent block per CU), as many groups as the
+    // device holds at once, up to kMultiGraphs requests per launch taken from the launch's queue
+    s->group = s->opt.multi_group > 0 ? s->opt.multi_group : std::max(1, s->info.ncu / 8);
     {
         int occ = 0;
         if (multi_occupancy((base_flags(s->opt, 0, 0) & F_WAVE) != 0, s->opt.block, &occ) != hipSuccess || occ < 1)
             return bail(fail(MCM_EHIP, "multi-graph kernel cannot be resident with block %d", s->opt.block));
-        s->multi_max = std::max(1, std::min(kMultiMax, s->info.ncu * occ / s->group));
+        s->group = std::min(s->group, s->info.ncu * occ);
+        s->ngroups = std::max(1, std::min(kMultiMax, s->info.ncu * occ / s->group));
     }
-    const int ndesc = std::max(max_batch, kMultiMax);
+    const int ndesc = std::max(max_batch, kMultiGraphs);
+    s->multi_max = kMultiGraphs;
     s->slots.resize(2);
     for (auto &sl : s->slots) {
         if (hipMalloc(&sl.d_desc, sizeof(BatchDesc) * ndesc) != hipSuccess ||

@@ -145,3 +145,27 @@ def test_large_members_in_multi_graph_launches(group):
         total0, cards0, cm0, rm0 = mcm.match_batched(b)
         assert cards0.tolist() == refs
     _check_outputs(graphs, cm0, rm0, cards0)
+
+
+@pytest.mark.parametrize("barrier", ["counter", "flags"])
+def test_multi_graph_queue_runs_several_graphs_per_group(barrier):
+    """More large members than block groups: every group takes graph after
+    graph from the launch's queue (4 groups of 64 blocks, 22 large graphs of
+    both kinds, plus degenerate ones), continuing its barrier epochs across
+    graphs; every result equals the oracle's."""
+    graphs = [gg.uniform(18000 + 500 * k, 17000 + 300 * k, 3 + k % 3, 60 + k) for k in range(16)]
+    graphs += [gg.rmat(15, 6 << 15, 70 + k, n_limit=20000 + 1000 * k) for k in range(4)]
+    graphs += [gg.empty(40000, 0), gg.empty(20000, 20000), gg.grid5(150, 600, 600, 9)]
+    assert sum(g.nc + g.nr > (1 << 15) for g in graphs) >= 22
+    refs = [O.hopcroft_karp(g, *O.cheap_init(g))[0] for g in graphs]
+    b = mcm.pack_batch(graphs)
+    mcm.set_option("multi_group", 64)
+    mcm.set_option("barrier", barrier)
+    try:
+        for _ in range(2):
+            total, cards, cm, rm = mcm.match_batched(b)
+            torch.cuda.synchronize()
+            assert cards.tolist() == refs
+            _check_outputs(graphs, cm, rm, cards)
+    finally:
+        mcm.set_option("barrier", "counter")
