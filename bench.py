@@ -258,7 +258,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--batch-graphs", type=int, default=4096)
-    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--serve-requests", type=int, default=20000, help="serving trace length (after 1000 warm-up)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="serving: mean Poisson arrival rate, requests/s")
     ap.add_argument("--variants", default="",
                     help="instead of the bench line: the APFB/APsB x WR/plain x wave/thread grid on these "
                          "comma-separated workloads (one JSON line)")
@@ -382,7 +383,7 @@ def main():
     if not args.no_batched:
         out["batched"] = bench_batched(args.batch_graphs, max(args.steps, 3))
     if not args.no_serving:
-        out["serving"] = bench_serving(48, args.serve_requests, args.serve_requests // 8, 2000.0)
+        out["serving"] = bench_serving(48, args.serve_requests + 1000, 1000, args.serve_rate)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, cm0, rm0, args.cpu_budget)
         out["cpu_baseline"]["cores"] = 1

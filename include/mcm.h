@@ -99,8 +99,9 @@ typedef struct {
  * mcm_match_batched -- maximum matchings of many independent graphs in one
  * device launch (one persistent kernel drains a work queue of graphs,
  * largest first; each graph is matched by one workgroup with the same
- * phases as mcm_match).  Members with ncols + nrows above the option
- * "multi_threshold" (default 2^15) are matched instead, after the
+ * phases as mcm_match).  Members with ncols + nrows above both the option
+ * "multi_threshold" (default 2^15) and twice the batch's vertices per
+ * resident workgroup are matched instead, after the
  * workgroup kernel on the same stream, by one cooperative launch whose
  * groups of "multi_group" blocks (default: an eighth of the CUs) take them
  * from a queue.  Defined to equal calling mcm_match on each graph: the per-graph

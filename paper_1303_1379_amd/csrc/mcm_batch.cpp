@@ -206,11 +206,21 @@ int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs, const int32_
     // Members above multi_threshold vertices are matched by groups of blocks,
     // several graphs per cooperative launch; the order is largest first, so
     // they are its prefix.
+    // A member also has to exceed twice the average load of a resident
+    // workgroup: with many graphs the workgroup kernel spreads even the
+    // larger ones over all CUs, and the multi-graph launch, which runs
+    // after it, would only add its own length.
     int32_t nlarge = 0;
+    int64_t large_min = o.multi_threshold;
+    if (o.multi_threshold > 0) {
+        int per_cu = 1;
+        if (match_wg_occupancy(o.mapping != 0, o.wg_block, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+        large_min = std::max<int64_t>(large_min, 2 * ex.verts / std::max(1, w.info.ncu * per_cu));
+    }
     if (o.multi_threshold > 0)
         while (nlarge < ngraphs) {
             const mcm_graph &g = graphs[w.h_order[nlarge]];
-            if ((int64_t)g.ncols + g.nrows <= o.multi_threshold) break;
+            if ((int64_t)g.ncols + g.nrows <= large_min) break;
             w.h_desc[ngraphs + nlarge] = w.h_desc[w.h_order[nlarge]];
             ++nlarge;
         }
