@@ -271,8 +271,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(graphs shard by independent batches across GPUs, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported (independent graphs and "
+              "requests would shard across GPUs with no exchange; one GPU's share is what is measured)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
