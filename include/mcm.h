@@ -351,6 +351,8 @@ typedef struct {
     double  kernel_ms;       /* device time of the matching, HIP events */
     int32_t loop;            /* 0 = device-side level loop, 1 = host-side */
     int32_t mapping;         /* 0 = thread, 1 = wave */
+    int64_t claims_tried;    /* compare-and-swaps on rows the probe saw unreached (stats=1);
+                                claims_tried - cols_claimed - rows_found were lost to another lane */
 } mcm_stats;
 
 int mcm_last_stats(mcm_stats *out);

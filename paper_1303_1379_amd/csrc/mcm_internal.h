@@ -26,14 +26,14 @@ enum CtrlLine : int {
     L_BAR_CNT1,
     L_TAKE,            // multi-graph launch: the graph a group's block 0 took from the queue
     L_STAT0,           // stats counters (64-bit each, own lines)
-    L_NLINES = L_STAT0 + 12
+    L_NLINES = L_STAT0 + 13
 };
 constexpr int kLineWords = 32;        // 128 B / 4 B
 constexpr int kPhaseTrace = 4096;     // phases whose (levels, ends) a stats run records
 constexpr int kMaxGridBlocks = 2048;  // arrival flags of the grid barrier, one line each
 
 enum StatIdx : int {
-    S_EDGES = 0, S_EXPANDED, S_CLAIMED, S_FOUND, S_ALT, S_FIX, S_ROOTS,
+    S_EDGES = 0, S_EXPANDED, S_CLAIMED, S_FOUND, S_ALT, S_FIX, S_ROOTS, S_TRIES,
     S_T_EXPAND, S_T_FLUSH, S_T_BARRIER, S_T_SMALL, S_T_AUGMENT  // wall-clock ticks seen by block 0 (stats=1)
 };
 

@@ -129,6 +129,10 @@ DEV Stage make_stage(char *smem)
     return s;
 }
 
+// Word of the staging scratch that holds a level's batch counter (words
+// 0..51 serve block_flush).
+constexpr int kBatchCtr = 52;
+
 DEV uint32_t *stage_tmp(char *smem)
 {
     const int waves = blockDim.x >> 6;
@@ -208,7 +212,7 @@ DEV uint32_t block_flush(Stage &st, int4 *gq, uint32_t *gqcnt, int32_t *ge, uint
 // claimed as an augmenting-path end (rmatch = -2) and marks its root done.
 template <int S>
 DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, int level, uint32_t flags,
-                    bool &newcol, int4 &ne, bool &newend)
+                    bool &newcol, int4 &ne, bool &newend, bool &tried)
 {
     // agent scope reads the memory-side copy, which other XCDs' claims
     // update; a stale L2 copy would send every scanner of a popular row
@@ -216,6 +220,7 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
     const uint64_t w = (S == kAgent) ? __hip_atomic_load(&g.rw[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : g.rw[r];
     if ((uint32_t)(w >> 32) == ph) return;           // reached earlier in this phase
     const int mate = (int)(uint32_t)w;
+    tried = mate >= -1;                               // a compare-and-swap follows
     if (mate >= 0) {
         // adjacency range of the column behind r, fetched alongside the claim
         const int b = g.colptr[mate], e = g.colptr[mate + 1];
@@ -257,7 +262,7 @@ DEV void add_stat(uint64_t *stats, int idx, uint64_t v)
 // holds them through the run: a count is reduced over the wavefront and
 // added by its first lane (wavefront-uniform calls, all lanes active); the
 // timers (StatIdx S_T_*) are kept by thread 0.  Indices are StatIdx.
-constexpr int kAccN = 12;
+constexpr int kAccN = 13;
 
 struct Acc {
     uint64_t *c;  // LDS [kAccN]
@@ -287,10 +292,12 @@ struct Acc {
     }
 };
 
-// Zeroed counters; every thread of the workgroup calls it.
-DEV Acc make_acc(uint64_t *lds)
+// Zeroed counters (and the level batch counter in the staging scratch,
+// when given); every thread of the workgroup calls it.
+DEV Acc make_acc(uint64_t *lds, uint32_t *s_tmp = nullptr)
 {
     if (threadIdx.x < (unsigned)kAccN) lds[threadIdx.x] = 0;
+    if (s_tmp && threadIdx.x == 0) s_tmp[kBatchCtr] = 0;
     __syncthreads();
     return Acc{lds};
 }
@@ -344,7 +351,17 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
     // waits for the cdone load); late (wave mapping): the scan and the
     // rowind loads go ahead and the claims of such an entry are skipped.
     const bool late = WAVE && (flags & F_WR) && (flags & F_WR_LATE);
-    for (uint32_t base = wave * B; base < n; base += nwaves * B) {
+    // Batches: with at most one per wavefront (small frontiers), wavefront w
+    // takes batch w.  With more, the batches of a workgroup are blk,
+    // blk + nblk, blk + 2 nblk, ... (interleaved over the workgroups) and its
+    // wavefronts take them in turn from an LDS counter, so that a wavefront
+    // that drew light batches takes more (R-MAT batches range from 64 to
+    // thousands of edges).
+    const uint32_t wpb = blockDim.x >> 6, blk = wave / wpb, nblk = nwaves / wpb;
+    const bool dyn = (uint64_t)nwaves * B < n;
+    uint32_t *ctr = s_tmp + kBatchCtr;
+    // one batch of entries [base, base + B) of the frontier
+    auto batch = [&](const uint32_t base) {
         const uint32_t i = base + lane;
         int4 e = make_int4(0, 0, 0, 0);
         int deg = 0;
@@ -377,39 +394,61 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
                 const int oroot = __shfl(e.y, own, 64);
                 const int obeg = __shfl(e.z, own, 64);
                 const int oexcl = __shfl(excl, own, 64);
-                bool newcol = false, newend = false;
+                bool newcol = false, newend = false, tried = false;
                 int4 ne = make_int4(0, 0, 0, 0);
                 int r = 0;
                 if (k < total) {
                     r = g.rowind[obeg + (k - oexcl)];
                     const uint32_t odone = late ? (uint32_t)__shfl((int)rdone, own, 64) : 0u;
-                    if (!late || odone != ph) visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend);
+                    if (!late || odone != ph)
+                        visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend, tried);
                 }
                 push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
                 stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt, st.de);
                 any_end |= newend;
-                if (flags & F_STATS) { acc.add(S_CLAIMED, newcol ? 1u : 0u); acc.add(S_FOUND, newend ? 1u : 0u); }
+                if (flags & F_STATS) {
+                    acc.add(S_CLAIMED, newcol ? 1u : 0u);
+                    acc.add(S_FOUND, newend ? 1u : 0u);
+                    acc.add(S_TRIES, tried ? 1u : 0u);
+                }
             }
         } else {
             const int maxdeg = wave_max(deg);
             for (int t = 0; t < maxdeg; ++t) {
-                bool newcol = false, newend = false;
+                bool newcol = false, newend = false, tried = false;
                 int4 ne = make_int4(0, 0, 0, 0);
                 int r = 0;
                 if (t < deg) {
                     r = g.rowind[e.z + t];
-                    visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend);
+                    visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend, tried);
                 }
                 push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
                 stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt, st.de);
                 any_end |= newend;
-                if (flags & F_STATS) { acc.add(S_CLAIMED, newcol ? 1u : 0u); acc.add(S_FOUND, newend ? 1u : 0u); }
+                if (flags & F_STATS) {
+                    acc.add(S_CLAIMED, newcol ? 1u : 0u);
+                    acc.add(S_FOUND, newend ? 1u : 0u);
+                    acc.add(S_TRIES, tried ? 1u : 0u);
+                }
             }
         }
+        };
+    if (dyn) {
+        for (;;) {
+            uint32_t k = 0;
+            if (lane == 0) k = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            k = __shfl(k, 0, 64);
+            const uint64_t base64 = ((uint64_t)blk + (uint64_t)k * nblk) * B;
+            if (base64 >= n) break;
+            batch((uint32_t)base64);
+        }
+    } else if (wave * B < n) {
+        batch(wave * B);
     }
     if ((flags & F_APSB) && __ballot(any_end) != 0 && lane == 0) atomicOr(io.found, 1u);
     const uint64_t t1 = (flags & F_STATS) ? wall_clock64() : 0;
     const uint32_t added = block_flush(st, io.nfq, io.ncnt, g.ends, io.ecnt, s_tmp);
+    if (threadIdx.x == 0) *ctr = 0;  // every wavefront is past it (the flush ends with a barrier)
     if (flags & F_STATS) { acc.tick(S_T_EXPAND, t1 - t0); acc.tick(S_T_FLUSH, wall_clock64() - t1); }
     return added;
 }
@@ -944,7 +983,7 @@ __global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl,
     Stage st = make_stage(smem);
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
-    Acc acc = make_acc(s_acc);
+    Acc acc = make_acc(s_acc, stage_tmp(smem));
     uint32_t ph = 0, lv = 0, epoch = 0;
     if (run_grid<WAVE>(g, ctrl, bar, o, stats, acc, st, s_tmp, s_loc, &s_ok, &ph, &lv, Grp{blockIdx.x, gridDim.x},
                        epoch) &&
@@ -1031,7 +1070,7 @@ __global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *desc
     Stage st = make_stage(smem);
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));
-    Acc acc = make_acc(s_acc);
+    Acc acc = make_acc(s_acc, stage_tmp(smem));
     const bool leader = gr.b == 0 && threadIdx.x == 0;
     auto always = [](const LvState &) -> bool { return true; };
     const bool counter = (o.flags & F_BAR_COUNTER) != 0;
@@ -1113,7 +1152,7 @@ __global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint
     LevelIO io{(L & 1) ? g.fq0 : g.fq1, line(ctrl, L_FCOUNT0 + (L + 1) % 3), line(ctrl, L_NENDS),
                line(ctrl, L_FOUND0 + L % 3)};
     __shared__ uint64_t s_acc[kAccN];
-    Acc acc = make_acc(s_acc);
+    Acc acc = make_acc(s_acc, stage_tmp(smem));
     expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
     if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
 }
@@ -1200,7 +1239,7 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
     __shared__ int32_t s_next;
     __shared__ uint32_t s_m;
     __shared__ uint64_t s_acc[kAccN];
-    Acc acc = make_acc(s_acc);
+    Acc acc = make_acc(s_acc, stage_tmp(smem));
     Stage st = make_stage(smem);
     uint32_t *s_tmp = stage_tmp(smem);
     uint64_t *stats = reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0));

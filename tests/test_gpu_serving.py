@@ -57,7 +57,7 @@ def test_alone_equals_mix_equals_oracle():
         assert card == alone[i] == refs[i]
         assert O.check_matching(gs[i], cm, rm) == card
         assert info["path"] == (1 if gs[i].nc + gs[i].nr > (1 << 15) else 0)
-        assert 1 <= info["batch_size"] <= (8 if info["path"] == 1 else 256)
+        assert 1 <= info["batch_size"] <= (64 if info["path"] == 1 else 256)
     st = s.stats()
     assert st["completed"] == st["submitted"] == len(gs) * 4
     assert st["launches_grid"] >= 2 and st["max_batch_seen"] >= 2
@@ -76,7 +76,7 @@ def test_large_requests_share_multi_graph_launches():
         assert card == refs[k // 2]
         assert O.check_matching(gs[k // 2], cm, rm) == card
         assert info["path"] == 1
-        assert 1 <= info["batch_size"] <= 8
+        assert 1 <= info["batch_size"] <= 64  # large requests per multi-graph launch, at most
     st = s.stats()
     assert st["launches_grid"] <= len(tickets) and st["completed"] == len(tickets)
     s.close()
