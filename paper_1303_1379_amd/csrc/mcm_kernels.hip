@@ -133,6 +133,10 @@ DEV Stage make_stage(char *smem)
 // 0..51 serve block_flush).
 constexpr int kBatchCtr = 52;
 
+// Elements per lane in flight in the per-phase passes over all columns or
+// rows (the roots, FixMatching).
+constexpr int kStream = 4;
+
 DEV uint32_t *stage_tmp(char *smem)
 {
     const int waves = blockDim.x >> 6;
@@ -463,20 +467,29 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
 {
     const int lane = __lane_id();
     const uint32_t flags = o.flags;
-    for (uint32_t base = wave * 64u; base < (uint32_t)g.nc; base += nwaves * 64u) {
-        const int c = (int)(base + lane);
-        bool p = false;
-        int4 e = make_int4(0, 0, 0, 0);
-        if (c < g.nc) {
-            const bool un = g.cmatch[c] == -1;
-            if (un) {
-                const int b = g.colptr[c], en = g.colptr[c + 1];
-                if (en > b) { p = true; e = make_int4(c, c, b, en); }
-            }
-            if (flags & F_LEVELS) g.clevel[c] = un ? 0 : -1;
+    const uint32_t nc = (uint32_t)g.nc;
+    // kStream chunks of 64 columns per wavefront and step, their loads
+    // issued together (indices clamped, so every load is in bounds and
+    // unconditional; a clamped lane is masked afterwards)
+    for (uint32_t base = wave * 64u * kStream; base < nc; base += nwaves * 64u * kStream) {
+        int cm[kStream], b[kStream], en[kStream];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) {
+            const uint32_t c = min(base + 64u * u + (uint32_t)lane, nc - 1);
+            cm[u] = g.cmatch[c];
+            b[u] = g.colptr[c];
+            en[u] = g.colptr[c + 1];
         }
-        if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
-        push_entry(p, e, o.split, st, g.fq0, cnt);
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) {
+            const uint32_t c = base + 64u * u + (uint32_t)lane;
+            const bool in = c < nc, un = in && cm[u] == -1;
+            const bool p = un && en[u] > b[u];
+            const int4 e = make_int4((int)c, (int)c, b[u], en[u]);
+            if ((flags & F_LEVELS) && in) g.clevel[c] = un ? 0 : -1;
+            if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
+            push_entry(p, e, o.split, st, g.fq0, cnt);
+        }
     }
     block_flush(st, g.fq0, cnt, g.ends, nullptr, s_tmp);
 }
@@ -518,10 +531,21 @@ DEV void fix_matching(const DevGraph &g, uint32_t tid, uint32_t nthreads, uint32
 {
     uint64_t resets = 0;
     int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);
-    for (uint32_t r = tid; r < (uint32_t)g.nr; r += nthreads) {
-        const int m = rlo[2 * (size_t)r];
-        if (m == -1) continue;
-        if (m < 0 || g.cmatch[m] != (int)r) { rlo[2 * (size_t)r] = -1; resets += (m >= 0); }
+    const uint32_t nr = (uint32_t)g.nr;
+    // kStream rows per thread and step: their words, then their columns'
+    // mates, loaded together (clamped indices, masked afterwards)
+    for (uint32_t r0 = tid; r0 < nr; r0 += nthreads * kStream) {
+        int m[kStream], cm[kStream];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) m[u] = rlo[2 * (size_t)min(r0 + u * nthreads, nr - 1)];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) cm[u] = g.cmatch[m[u] >= 0 ? m[u] : 0];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) {
+            const uint32_t r = r0 + u * nthreads;
+            if (r >= nr || m[u] == -1) continue;
+            if (m[u] < 0 || cm[u] != (int)r) { rlo[2 * (size_t)r] = -1; resets += (m[u] >= 0); }
+        }
     }
     if (flags & F_STATS) acc.add(S_FIX, resets);
 }
