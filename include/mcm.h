@@ -298,6 +298,20 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              persistent launch with grid
  *                                              barriers, or one launch per
  *                                              level
+ *   "claim"     "auto" (default) | "max" | "probe"
+ *                                              how a BFS claims a row (the
+ *                                              visited check of Algorithm 2,
+ *                                              made atomic): one 64-bit
+ *                                              atomic maximum of the phase
+ *                                              stamp, or a load of the row
+ *                                              word then a compare-and-swap
+ *                                              (fewer atomics on rows with
+ *                                              many edges); auto = max when
+ *                                              the graph has at most 8 edges
+ *                                              per row on average.  mcm_match
+ *                                              above the one-workgroup size
+ *                                              only; max keeps 8 bytes per
+ *                                              row more workspace
  *   "validate"  "0" (default) | "1"            check CSC and init on device
  *   "stats"     "0" (default) | "1"            count scanned edges etc.
  *   "tuning"    path of an autotuner cache file (JSON lines) or ""

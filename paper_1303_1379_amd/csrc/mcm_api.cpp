@@ -126,6 +126,21 @@ int64_t ensure_graph(Workspace &w, size_t nc, size_t nr, size_t qcap)
     return 0;
 }
 
+// Mate adjacency ranges for nr rows (atomic-maximum claims only).
+static int64_t ensure_radj(Workspace &w, size_t nr)
+{
+    if (nr <= w.cap_radj) return 0;
+    free_dev(w.radj);
+    w.radj = nullptr;
+    const size_t cap = std::max(nr, w.cap_radj + w.cap_radj / 2);
+    if (hipMalloc(&w.radj, sizeof(int2) * cap) != hipSuccess) {
+        w.cap_radj = 0;
+        return fail(MCM_ENOMEM, "workspace allocation for %zu row ranges failed", nr);
+    }
+    w.cap_radj = cap;
+    return 0;
+}
+
 int64_t ensure_desc(Workspace &w, size_t n)
 {
     if (n <= w.cap_desc) return 0;
@@ -152,15 +167,18 @@ uint32_t *ctrl_line(uint32_t *ctrl, int l) { return ctrl + l * kLineWords; }
 
 // Frontier entries per level: one per column, plus one per `split` edges
 // of a split column.  Reads nnz = colptr[nc] from the device.
-int64_t queue_capacity(int32_t nc, const int32_t *colptr, uint32_t split, hipStream_t st, size_t *qcap)
+int64_t queue_capacity(int32_t nc, const int32_t *colptr, uint32_t split, hipStream_t st, size_t *qcap,
+                       int64_t *nnz_out)
 {
     *qcap = (size_t)nc + 1;
-    if (split == 0) return 0;
+    if (nnz_out) *nnz_out = -1;
+    if (split == 0 && !nnz_out) return 0;
     int32_t nnz = 0;
     HIPCHK(hipMemcpyAsync(&nnz, colptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (nnz < 0) return fail(MCM_EINVAL, "colptr[ncols] = %d < 0", nnz);
-    *qcap += (size_t)nnz / split + 1;
+    if (nnz_out) *nnz_out = nnz;
+    if (split != 0) *qcap += (size_t)nnz / split + 1;
     return 0;
 }
 uint64_t ctrl_stat(uint32_t *ctrl, int s) { return reinterpret_cast<uint64_t *>(ctrl_line(ctrl, L_STAT0))[s * 16]; }
@@ -461,6 +479,11 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "one") g_opt.endpoints = 1;
         else if (v == "auto") g_opt.endpoints = 2;
         else return (int)fail(MCM_EINVAL, "endpoints must be all, one or auto");
+    } else if (k == "claim") {
+        if (v == "probe") g_opt.claim = 0;
+        else if (v == "max") g_opt.claim = 1;
+        else if (v == "auto") g_opt.claim = 2;
+        else return (int)fail(MCM_EINVAL, "claim must be probe, max or auto");
     } else if (k == "barrier") {
         if (v == "flags") g_opt.bar_counter = false;
         else if (v == "counter") g_opt.bar_counter = true;
@@ -519,6 +542,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "wr_check") v = o.wr_late ? "late" : "early";
     else if (k == "barrier") v = o.bar_counter ? "counter" : "flags";
     else if (k == "endpoints") v = o.endpoints == 0 ? "all" : (o.endpoints == 1 ? "one" : "auto");
+    else if (k == "claim") v = o.claim == 0 ? "probe" : (o.claim == 1 ? "max" : "auto");
     else if (k == "multi_group") v = std::to_string(o.multi_group);
     else if (k == "batch_min") v = std::to_string(o.batch_min);
     else if (k == "split") v = std::to_string(o.split);
@@ -598,7 +622,10 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     if ((rc = ensure_base(w, dev))) return rc;
     const bool single_wg = (int64_t)ncols + nrows <= o.wg_threshold;
     size_t qcap = 0;
-    if ((rc = queue_capacity(ncols, colptr, single_wg ? 0u : (uint32_t)o.split, st, &qcap))) return rc;
+    int64_t nnz = -1;
+    if ((rc = queue_capacity(ncols, colptr, single_wg ? 0u : (uint32_t)o.split, st, &qcap,
+                             single_wg || o.claim != 2 ? nullptr : &nnz)))
+        return rc;
     if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows, std::max(qcap, (size_t)ncols)))) return rc;
 
     if (o.validate) {
@@ -611,7 +638,13 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
         if (s == MCM_EBADINIT) return fail(MCM_EBADINIT, "initial matching is inconsistent or not on edges");
     }
 
-    const uint32_t flags = base_flags(o, ncols, 0);
+    uint32_t flags = base_flags(o, ncols, 0);
+    // Atomic-maximum claims where rows have few edges: a row then has few
+    // visitors per phase and the atomic replaces a probe plus a
+    // compare-and-swap.  Hub rows (skewed degrees) keep the probe, which lets
+    // all but the first visitor of a level skip the atomic.
+    if (!single_wg && (o.claim == 1 || (o.claim == 2 && nnz >= 0 && nnz <= kMaxClaimDegree * (int64_t)nrows)))
+        flags |= F_MAXCLAIM;
     int loop = 0;
     float ms = 0.f;
     int64_t init_card = -1;
@@ -643,6 +676,10 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     g.ends = w.ends;
     g.clevel = nullptr;
     g.ptrace = (flags & F_STATS) ? w.ptrace : nullptr;
+    if (flags & F_MAXCLAIM) {
+        if ((rc = ensure_radj(w, (size_t)nrows))) return rc;
+        g.radj = w.radj;
+    }
     HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, w.bar, flags, st));
     if ((rc = run_graph(w, o, g, flags, st, &loop))) return rc;
     HIPCHK(launch_finish(g, out_rmatch, w.ctrl, st));
@@ -665,7 +702,7 @@ static int64_t one_bfs_phase(Workspace &w, const Options &o, int32_t nc, int32_t
 {
     int64_t rc;
     size_t qcap = 0;
-    if ((rc = queue_capacity(nc, colptr, (uint32_t)o.split, st, &qcap))) return rc;
+    if ((rc = queue_capacity(nc, colptr, (uint32_t)o.split, st, &qcap, nullptr))) return rc;
     if ((rc = ensure_graph(w, (size_t)nc, (size_t)nr, qcap))) return rc;
     DevGraph g;
     g.colptr = colptr;

@@ -35,6 +35,7 @@ hipError_t match_wg_occupancy(bool wave, int block, int *per_cu);
 hipError_t launch_cheap_init(const BatchDesc *descs, int32_t ngraphs, hipStream_t st);
 hipError_t multi_occupancy(bool wave, int block, int *per_cu);
 constexpr int kMultiMax = 16;  // block groups (control blocks) of a multi-graph launch, upper bound
+constexpr int64_t kMaxClaimDegree = 8;  // claim=auto: atomic-maximum claims up to this many edges per row on average
 hipError_t launch_multi(const BatchDesc *descs, int32_t ngraphs, int group, int ngroups, uint32_t *ctrls,
                         uint32_t *bars, int64_t *card, const RunOpt &o, bool wave, int block, hipStream_t st);
 
@@ -58,6 +59,7 @@ struct Options {
     bool wr = true;           // bfs
     bool wr_late = true;      // WR root check beside the edge visit (wave mapping)
     int endpoints = 2;        // WR path ends per root: 0 all reached, 1 the first only, 2 auto (1 for APsB)
+    int claim = 2;            // row claim: 0 probe + compare-and-swap, 1 atomic maximum, 2 auto (by degree)
     int mapping = 2;          // 0 thread, 1 wave, 2 auto
     int loop = 2;             // 0 device, 1 host, 2 auto
     bool validate = false;
@@ -96,6 +98,8 @@ struct Workspace {
     uint32_t *cdone = nullptr;
     int4 *fq = nullptr;
     int32_t *ends = nullptr;
+    int2 *radj = nullptr;        // mate adjacency ranges (atomic-maximum claims), grown on demand
+    size_t cap_radj = 0;
     int32_t *cwork = nullptr;
     uint32_t *ctrl = nullptr;
     uint32_t *bar = nullptr;     // grid barrier arrival flags

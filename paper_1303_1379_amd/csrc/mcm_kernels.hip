@@ -218,6 +218,37 @@ template <int S>
 DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, int level, uint32_t flags,
                     bool &newcol, int4 &ne, bool &newend, bool &tried)
 {
+    if (flags & F_MAXCLAIM) {
+        // Low-degree rows: one atomic maximum of the phase stamp claims the
+        // row and returns its old word (a row already stamped this phase is
+        // left as it is); the mate's adjacency range comes from radj, loaded
+        // alongside.  Stamps only grow during a run, so exactly one visitor
+        // per phase sees an older stamp.  The winner puts the mate (or -2)
+        // back into the low word, which no one reads before the next grid
+        // barrier.
+        const int2 adj = g.radj[r];
+        const uint64_t old = __hip_atomic_fetch_max(&g.rw[r], (uint64_t)ph << 32, __ATOMIC_RELAXED, S);
+        if ((uint32_t)(old >> 32) == ph) return;
+        tried = true;
+        const int mate = (int)(uint32_t)old;
+        int32_t *lo = reinterpret_cast<int32_t *>(g.rw) + 2 * (size_t)r;
+        g.pred[r] = col;
+        if (mate >= 0) {
+            st_i<S>(lo, mate);
+            ne = make_int4(mate, root, adj.x, adj.y);
+            newcol = true;
+            if (flags & F_LEVELS) g.clevel[mate] = level + 1;
+        } else {
+            st_i<S>(lo, -2);
+            if ((flags & F_WR) && (flags & F_ENDPOINT)) {
+                newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
+            } else {
+                newend = true;
+                if (flags & F_WR) g.cdone[root] = ph;
+            }
+        }
+        return;
+    }
     // agent scope reads the memory-side copy, which other XCDs' claims
     // update; a stale L2 copy would send every scanner of a popular row
     // into a failing compare-and-swap
@@ -514,6 +545,9 @@ DEV void alternate(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nth
             if (r2 != -1 && c2 == c) break;  // c already flipped by another walk
             st_i<S>(&g.cmatch[c], r);
             st_i<S>(&rlo[2 * (size_t)r], c);
+            // every walk through r writes the same column (pred[r]), so the
+            // range always belongs to the row's mate
+            if (flags & F_MAXCLAIM) g.radj[r] = make_int2(g.colptr[c], g.colptr[c + 1]);
             ++steps;
             if (r2 == -1) break;             // reached the root
             r = r2;
@@ -961,8 +995,10 @@ __global__ void k_setup(DevGraph g, const int32_t *init_c, const int32_t *init_r
         if (flags & F_LEVELS) g.clevel[c] = -1;
     }
     for (uint32_t r = tid; r < (uint32_t)g.nr; r += nt) {
-        g.rw[r] = (uint64_t)(uint32_t)(init_r ? init_r[r] : -1);
+        const int m = init_r ? init_r[r] : -1;
+        g.rw[r] = (uint64_t)(uint32_t)m;
         if (flags & F_LEVELS) g.pred[r] = -1;
+        if (flags & F_MAXCLAIM) g.radj[r] = m >= 0 ? make_int2(g.colptr[m], g.colptr[m + 1]) : make_int2(0, 0);
     }
     for (uint32_t i = tid; i < (uint32_t)(L_NLINES * kLineWords); i += nt) ctrl[i] = 0;
     if (bar)

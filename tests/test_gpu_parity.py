@@ -30,7 +30,7 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto", barrier="counter")
+                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto", barrier="counter", claim="auto")
 
 
 @pytest.fixture(autouse=True)
@@ -194,6 +194,27 @@ def test_driver_variants(combo, name):
         _set(wg_threshold=thr, **combo)
         card, _, _ = _gpu(g)
         assert card == ref, (combo, thr)
+
+
+# Both ways of claiming a row, forced on graphs of either degree profile
+# (auto picks the atomic maximum for the grids and uniform graphs and the
+# probe for R-MAT): drivers, mappings, both level loops, both end rules,
+# single-workgroup runs of small levels on and off, cheap and empty starts.
+CLAIM_COMBOS = [dict(driver="apfb", mapping="wave", loop="device", endpoints="auto", small_max=256),
+                dict(driver="apfb", mapping="thread", loop="device", endpoints="one", small_max=0),
+                dict(driver="apsb", mapping="wave", loop="device", endpoints="auto", small_max=0),
+                dict(driver="apsb", mapping="thread", loop="host", endpoints="all", small_max=256),
+                dict(driver="apfb", mapping="wave", loop="host", endpoints="auto", small_max=256)]
+
+
+@pytest.mark.parametrize("claim", ["max", "probe"])
+@pytest.mark.parametrize("combo", CLAIM_COMBOS, ids=lambda c: "-".join(str(v) for v in c.values()))
+@pytest.mark.parametrize("name", ["uniform2000", "grid128", "grid256p", "rmat13"])
+def test_claim_modes(claim, combo, name):
+    g = gg.workload(name)
+    _set(wg_threshold=0, claim=claim, **combo)
+    assert _gpu(g)[0] == _oracle_card(g), (claim, combo)
+    assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (claim, combo)
 
 
 # Grid levels with a varying number of participating blocks: every block
