@@ -312,6 +312,22 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              above the one-workgroup size
  *                                              only; max keeps 8 bytes per
  *                                              row more workspace
+ *   "flush"     "auto" (default) | "defer" | "atomic"
+ *                                              how a level of the persistent
+ *                                              loop reserves its next
+ *                                              frontier: with the counter
+ *                                              barrier's own addition, the
+ *                                              entries written after
+ *                                              arriving and checked by their
+ *                                              readers, and the barriers
+ *                                              between two such levels
+ *                                              without memory fences (defer;
+ *                                              needs "barrier" "counter"), or
+ *                                              with one queue atomic per
+ *                                              workgroup before arriving;
+ *                                              auto = defer when the graph
+ *                                              has at most 8 edges per row
+ *                                              on average
  *   "validate"  "0" (default) | "1"            check CSC and init on device
  *   "stats"     "0" (default) | "1"            count scanned edges etc.
  *   "tuning"    path of an autotuner cache file (JSON lines) or ""

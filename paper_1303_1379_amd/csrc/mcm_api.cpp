@@ -207,6 +207,7 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
     int loop = o.loop;
     if (loop == 2) loop = 0;
     *loop_used = loop;
+    if (loop != 0) flags &= ~(uint32_t)F_DEFER;  // deferred writes belong to the persistent level loop
     RunOpt ro = run_opt(o, flags, g.nc, w.info);
     if (loop == 0) {
         int occ = 0;
@@ -479,6 +480,11 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "one") g_opt.endpoints = 1;
         else if (v == "auto") g_opt.endpoints = 2;
         else return (int)fail(MCM_EINVAL, "endpoints must be all, one or auto");
+    } else if (k == "flush") {
+        if (v == "atomic") g_opt.flush = 0;
+        else if (v == "defer") g_opt.flush = 1;
+        else if (v == "auto") g_opt.flush = 2;
+        else return (int)fail(MCM_EINVAL, "flush must be atomic, defer or auto");
     } else if (k == "claim") {
         if (v == "probe") g_opt.claim = 0;
         else if (v == "max") g_opt.claim = 1;
@@ -543,6 +549,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "barrier") v = o.bar_counter ? "counter" : "flags";
     else if (k == "endpoints") v = o.endpoints == 0 ? "all" : (o.endpoints == 1 ? "one" : "auto");
     else if (k == "claim") v = o.claim == 0 ? "probe" : (o.claim == 1 ? "max" : "auto");
+    else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
     else if (k == "multi_group") v = std::to_string(o.multi_group);
     else if (k == "batch_min") v = std::to_string(o.batch_min);
     else if (k == "split") v = std::to_string(o.split);
@@ -624,7 +631,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     size_t qcap = 0;
     int64_t nnz = -1;
     if ((rc = queue_capacity(ncols, colptr, single_wg ? 0u : (uint32_t)o.split, st, &qcap,
-                             single_wg || o.claim != 2 ? nullptr : &nnz)))
+                             single_wg || (o.claim != 2 && o.flush != 2) ? nullptr : &nnz)))
         return rc;
     if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows, std::max(qcap, (size_t)ncols)))) return rc;
 
@@ -643,8 +650,15 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     // visitors per phase and the atomic replaces a probe plus a
     // compare-and-swap.  Hub rows (skewed degrees) keep the probe, which lets
     // all but the first visitor of a level skip the atomic.
-    if (!single_wg && (o.claim == 1 || (o.claim == 2 && nnz >= 0 && nnz <= kMaxClaimDegree * (int64_t)nrows)))
-        flags |= F_MAXCLAIM;
+    const bool low_degree = nnz >= 0 && nnz <= kMaxClaimDegree * (int64_t)nrows;
+    if (!single_wg && (o.claim == 1 || (o.claim == 2 && low_degree))) flags |= F_MAXCLAIM;
+    // Persistent level loop with the counter barrier: a grid level's next
+    // frontier is reserved by the barrier's own addition, and grid levels
+    // pass their barriers without fences (what they share is in agent-scope
+    // atomics).  It pays where levels are many and small (low degree); on
+    // skewed graphs (few, large levels) the per-entry checks cost more.
+    if (!single_wg && o.bar_counter && o.loop != 1 && (o.flush == 1 || (o.flush == 2 && low_degree)))
+        flags |= F_DEFER;
     int loop = 0;
     float ms = 0.f;
     int64_t init_card = -1;
@@ -680,6 +694,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
         if ((rc = ensure_radj(w, (size_t)nrows))) return rc;
         g.radj = w.radj;
     }
+    g.qcap = w.cap_q;
     HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, w.bar, flags, st));
     if ((rc = run_graph(w, o, g, flags, st, &loop))) return rc;
     HIPCHK(launch_finish(g, out_rmatch, w.ctrl, st));

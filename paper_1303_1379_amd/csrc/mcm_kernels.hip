@@ -60,6 +60,7 @@ DEV uint32_t *line(uint32_t *ctrl, int l) { return ctrl + l * kLineWords; }
 template <int S> DEV uint32_t ld_u(const uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, S); }
 template <int S> DEV int32_t ld_i(const int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, S); }
 template <int S> DEV void st_i(int32_t *p, int32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, S); }
+template <int S> DEV void st_u(uint32_t *p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, S); }
 template <int S> DEV bool cas_u64(uint64_t *p, uint64_t expect, uint64_t desired)
 {
     return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED, S);
@@ -143,43 +144,146 @@ DEV uint32_t *stage_tmp(char *smem)
     return reinterpret_cast<uint32_t *>(smem + waves * (kStageQ * 16 + kStageE * 4));
 }
 
-template <class T>
-DEV void stage_drain(T *buf, int &n, T *gq, uint32_t *gcnt, int &drained)
+// An unmatched-row end; agent scope (`atomic`) where grid levels pass their
+// barriers without fences (F_DEFER).
+DEV void put_end(int32_t *ge, uint32_t i, int32_t r, bool atomic)
+{
+    if (atomic) __hip_atomic_store(ge + i, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else ge[i] = r;
+}
+
+// Hand a wavefront's staged ends to the global list now (its stage is full).
+DEV void drain_ends(Stage &st, int32_t *ge, uint32_t *gcnt, bool atomic)
 {
     wave_lds_sync();
     uint32_t base = 0;
-    if (__lane_id() == 0) base = atomicAdd(gcnt, (uint32_t)n);
+    if (__lane_id() == 0) base = atomicAdd(gcnt, (uint32_t)st.ne);
     base = __shfl(base, 0, 64);
-    for (int i = __lane_id(); i < n; i += 64) gq[base + i] = buf[i];
+    for (int i = __lane_id(); i < st.ne; i += 64) put_end(ge, base + i, st.e[i], atomic);
     wave_lds_sync();
-    drained += n;
-    n = 0;
+    st.de += st.ne;
+    st.ne = 0;
 }
 
-// Append `item` for every lane with p set (wavefront-uniform call).
-template <class T, int CAP>
-DEV void stage_push(bool p, const T &item, T *buf, int &n, T *gq, uint32_t *gcnt, int &drained)
+// Append end r for every lane with p set (wavefront-uniform call).
+DEV void push_end(bool p, int32_t r, Stage &st, int32_t *ge, uint32_t *gcnt, bool atomic)
 {
     const uint64_t m = __ballot(p);
     if (m == 0) return;
-    if (n > CAP - 64) stage_drain(buf, n, gq, gcnt, drained);
-    if (p) buf[n + __popcll(m & lanemask_lt())] = item;
-    n += __popcll(m);
+    if (st.ne > kStageE - 64) drain_ends(st, ge, gcnt, atomic);
+    if (p) st.e[st.ne + __popcll(m & lanemask_lt())] = r;
+    st.ne += __popcll(m);
+}
+
+// Where a wavefront's frontier entries go: queue q, its slots reserved from
+// the 32-bit counter c32 or, for deferred grid levels, from the low word of
+// the 64-bit counter c64 of the coming grid barrier.  With `atomic` every
+// entry is stored as two agent-scope 64-bit words and read back by
+// take_entry: no copy of it waits in one XCD's L2, and a reader can tell a
+// slot that has not been written yet.
+struct QSink {
+    int4 *q;
+    uint32_t *c32;
+    uint64_t *c64;
+    bool atomic;
+};
+
+DEV void put_entry(const QSink &k, uint32_t i, const int4 &e)
+{
+    if (k.atomic) {
+        uint64_t *p = reinterpret_cast<uint64_t *>(k.q + i);
+        __hip_atomic_store(p, (uint64_t)(uint32_t)e.x | ((uint64_t)(uint32_t)e.y << 32), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(p + 1, (uint64_t)(uint32_t)e.z | ((uint64_t)(uint32_t)e.w << 32), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        k.q[i] = e;
+    }
+}
+
+// A consumed (or never written) slot of an atomic queue holds -1 in every
+// word; no entry has a negative column or edge start.
+constexpr uint64_t kNoEntry = ~0ull;
+
+// Entry i of an atomic queue, which its writer may still be storing: poll
+// (agent scope) until both words hold an entry, then leave -1 in the slot
+// for the next level that reuses the queue.  Bounded: on the wait limit or
+// a status it returns an entry with no edges (the next grid barrier then
+// ends the run).
+DEV int4 take_entry(int4 *q, uint32_t i, uint32_t *ctrl, uint64_t timeout)
+{
+    uint64_t *p = reinterpret_cast<uint64_t *>(q + i);
+    uint64_t a = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t b = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int32_t)(uint32_t)a < 0 || (int32_t)(uint32_t)b < 0) {
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+            __builtin_amdgcn_s_sleep(1);
+            a = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            b = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int32_t)(uint32_t)a >= 0 && (int32_t)(uint32_t)b >= 0) break;
+            if (status_of(ctrl) != 0) return make_int4(0, 0, 0, 0);
+            if (wall_clock64() - t0 > timeout) { set_status(ctrl, kEInternal); return make_int4(0, 0, 0, 0); }
+        }
+    }
+    __hip_atomic_store(p, kNoEntry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, kNoEntry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_int4((int)(uint32_t)a, (int)(uint32_t)(a >> 32), (int)(uint32_t)b, (int)(uint32_t)(b >> 32));
+}
+
+// Hand a wavefront's staged entries to the queue now (its LDS stage is full).
+DEV void drain_entries(Stage &st, const QSink &k)
+{
+    wave_lds_sync();
+    uint32_t base = 0;
+    if (__lane_id() == 0)
+        base = k.c64 ? (uint32_t)__hip_atomic_fetch_add(k.c64, (uint64_t)st.nq, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)
+                     : atomicAdd(k.c32, (uint32_t)st.nq);
+    base = __shfl(base, 0, 64);
+    for (int i = __lane_id(); i < st.nq; i += 64) put_entry(k, base + i, st.q[i]);
+    wave_lds_sync();
+    st.dq += st.nq;
+    st.nq = 0;
+}
+
+// Append frontier entry e for every lane with p set (wavefront-uniform call).
+DEV void push_q(bool p, const int4 &e, Stage &st, const QSink &k)
+{
+    const uint64_t m = __ballot(p);
+    if (m == 0) return;
+    if (st.nq > kStageQ - 64) drain_entries(st, k);
+    if (p) st.q[st.nq + __popcll(m & lanemask_lt())] = e;
+    st.nq += __popcll(m);
+}
+
+// The staged entries of wavefront w after a deferred flush: they go to
+// slots [base + s_tmp[w], ...), base being what the counter barrier's
+// addition returned to the workgroup.
+DEV void write_deferred(Stage &st, const QSink &k, uint32_t base, const uint32_t *s_tmp)
+{
+    const uint32_t off = base + s_tmp[threadIdx.x >> 6];
+    for (int i = __lane_id(); i < st.nq; i += 64) put_entry(k, off + i, st.q[i]);
+    st.nq = 0;
 }
 
 // End of a level: every wavefront of the workgroup hands its staged entries
 // to the global queues with one atomic per queue for the whole workgroup.
 // All threads of the workgroup call it.  Returns what the workgroup added
 // since the last flush: frontier entries in the low 31 bits, bit 31 set if
-// it added any unmatched-row end.
-DEV uint32_t block_flush(Stage &st, int4 *gq, uint32_t *gqcnt, int32_t *ge, uint32_t *gecnt, uint32_t *s_tmp)
+// it added any unmatched-row end.  Deferred (a grid level with F_DEFER):
+// the frontier entries stay staged, s_tmp[w] holds wavefront w's offset
+// among them, and the count returned is of the staged ones only (entries
+// drained earlier were reserved from the barrier counter already); the
+// unmatched-row ends are written as usual.
+DEV uint32_t block_flush(Stage &st, const QSink &k, int32_t *ge, uint32_t *gecnt, uint32_t *s_tmp, bool defer)
 {
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = __lane_id();
     wave_lds_sync();
     if (lane == 0) {
         s_tmp[w] = (uint32_t)st.nq;
         s_tmp[16 + w] = (uint32_t)st.ne;
-        s_tmp[36 + w] = (uint32_t)(st.dq + st.nq) | ((st.de + st.ne) > 0 ? 0x80000000u : 0u);
+        s_tmp[36 + w] = (uint32_t)(defer ? st.nq : st.dq + st.nq) | ((st.de + st.ne) > 0 ? 0x80000000u : 0u);
     }
     __syncthreads();
     if (w == 0) {
@@ -192,7 +296,10 @@ DEV uint32_t block_flush(Stage &st, int4 *gq, uint32_t *gqcnt, int32_t *ge, uint
         const bool any_end = __ballot((d >> 31) != 0) != 0;
         uint32_t bq = 0, be = 0;
         if (lane == 0) {
-            if (tq) bq = atomicAdd(gqcnt, tq);
+            if (tq && !defer)
+                bq = k.c64 ? (uint32_t)__hip_atomic_fetch_add(k.c64, (uint64_t)tq, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT)
+                           : atomicAdd(k.c32, tq);
             if (te) be = atomicAdd(gecnt, te);
         }
         if (lane < nw) { s_tmp[lane] = (uint32_t)(ia - a); s_tmp[16 + lane] = (uint32_t)(ib - b); }
@@ -201,9 +308,12 @@ DEV uint32_t block_flush(Stage &st, int4 *gq, uint32_t *gqcnt, int32_t *ge, uint
     __syncthreads();
     const uint32_t bq = s_tmp[32] + s_tmp[w], be = s_tmp[33] + s_tmp[16 + w];
     const uint32_t res = s_tmp[34];
-    for (int i = lane; i < st.nq; i += 64) gq[bq + i] = st.q[i];
-    for (int i = lane; i < st.ne; i += 64) ge[be + i] = st.e[i];
-    st.nq = st.ne = 0;
+    if (!defer) {
+        for (int i = lane; i < st.nq; i += 64) put_entry(k, bq + i, st.q[i]);
+        st.nq = 0;
+    }
+    for (int i = lane; i < st.ne; i += 64) put_end(ge, be + i, st.e[i], k.atomic);
+    st.ne = 0;
     st.dq = st.de = 0;
     __syncthreads();
     return res;
@@ -232,7 +342,7 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
         tried = true;
         const int mate = (int)(uint32_t)old;
         int32_t *lo = reinterpret_cast<int32_t *>(g.rw) + 2 * (size_t)r;
-        g.pred[r] = col;
+        st_i<S>(&g.pred[r], col);
         if (mate >= 0) {
             st_i<S>(lo, mate);
             ne = make_int4(mate, root, adj.x, adj.y);
@@ -244,7 +354,7 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
                 newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
             } else {
                 newend = true;
-                if (flags & F_WR) g.cdone[root] = ph;
+                if (flags & F_WR) st_u<S>(&g.cdone[root], ph);
             }
         }
         return;
@@ -260,31 +370,32 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
         // adjacency range of the column behind r, fetched alongside the claim
         const int b = g.colptr[mate], e = g.colptr[mate + 1];
         if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | (uint32_t)mate)) {
-            g.pred[r] = col;
+            st_i<S>(&g.pred[r], col);
             ne = make_int4(mate, root, b, e);
             newcol = true;
             if (flags & F_LEVELS) g.clevel[mate] = level + 1;
         }
     } else if (mate == -1) {
         if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | 0xFFFFFFFEull)) {
-            g.pred[r] = col;
+            st_i<S>(&g.pred[r], col);
             if ((flags & F_WR) && (flags & F_ENDPOINT)) {
                 // the root's path ends at the first unmatched row it reached;
                 // a later one stays marked and FixMatching frees it
                 newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
             } else {
                 newend = true;
-                if (flags & F_WR) g.cdone[root] = ph;
+                if (flags & F_WR) st_u<S>(&g.cdone[root], ph);
             }
         }
     }
 }
 
 struct LevelIO {
-    int4 *nfq;          // next frontier
-    uint32_t *ncnt;     // its size
+    QSink next;         // next frontier
     uint32_t *ecnt;     // ends found in this phase
     uint32_t *found;    // set when this level reached an unmatched row (APsB)
+    uint32_t *ctrl;     // status (waits on entries of an atomic queue)
+    bool defer;         // deferred flush (F_DEFER grid level)
 };
 
 DEV void add_stat(uint64_t *stats, int idx, uint64_t v)
@@ -356,11 +467,11 @@ DEV uint32_t batch_size(uint32_t n, uint32_t nwaves, uint32_t bmin)
 // with more than `split` edges goes in as consecutive entries of at most
 // `split` edges, so that the edges of one heavy column are expanded by
 // several wavefronts.  Wavefront-uniform call.
-DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, int4 *gq, uint32_t *gcnt)
+DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, const QSink &q)
 {
     const bool heavy = p && split != 0 && (uint32_t)(e.w - e.z) > split;
     if (__ballot(heavy) == 0) {
-        stage_push<int4, kStageQ>(p, e, st.q, st.nq, gq, gcnt, st.dq);
+        push_q(p, e, st, q);
         return;
     }
     const int nch = p ? (heavy ? (int)((e.w - e.z + split - 1) / split) : 1) : 0;
@@ -368,12 +479,12 @@ DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, int4 *gq, 
     for (int k = 0; k < maxk; ++k) {
         const int b = e.z + k * (int)split;
         const int en = heavy ? min(e.w, b + (int)split) : e.w;
-        stage_push<int4, kStageQ>(k < nch, make_int4(e.x, e.y, b, en), st.q, st.nq, gq, gcnt, st.dq);
+        push_q(k < nch, make_int4(e.x, e.y, b, en), st, q);
     }
 }
 
 template <bool WAVE, int S>
-DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
+DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
                           int level, const RunOpt &o, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc)
 {
     const int lane = __lane_id();
@@ -402,10 +513,10 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
         int deg = 0;
         uint32_t rdone = 0;
         if ((uint32_t)lane < B && i < n) {
-            e = fq[i];
+            e = io.next.atomic ? take_entry(fq, i, io.ctrl, o.timeout) : fq[i];
             deg = e.w - e.z;
-            if (late) rdone = g.cdone[e.y];
-            else if ((flags & F_WR) && deg > 0 && g.cdone[e.y] == ph) deg = 0;
+            if (late) rdone = ld_u<S>(&g.cdone[e.y]);
+            else if ((flags & F_WR) && deg > 0 && ld_u<S>(&g.cdone[e.y]) == ph) deg = 0;
         }
         if (flags & F_STATS) {
             const bool live = !(late && rdone == ph);
@@ -438,8 +549,8 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
                     if (!late || odone != ph)
                         visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend, tried);
                 }
-                push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
-                stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt, st.de);
+                push_entry(newcol, ne, o.split, st, io.next);
+                push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
                 any_end |= newend;
                 if (flags & F_STATS) {
                     acc.add(S_CLAIMED, newcol ? 1u : 0u);
@@ -457,8 +568,8 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
                     r = g.rowind[e.z + t];
                     visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend, tried);
                 }
-                push_entry(newcol, ne, o.split, st, io.nfq, io.ncnt);
-                stage_push<int32_t, kStageE>(newend, r, st.e, st.ne, g.ends, io.ecnt, st.de);
+                push_entry(newcol, ne, o.split, st, io.next);
+                push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
                 any_end |= newend;
                 if (flags & F_STATS) {
                     acc.add(S_CLAIMED, newcol ? 1u : 0u);
@@ -482,7 +593,7 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
     }
     if ((flags & F_APSB) && __ballot(any_end) != 0 && lane == 0) atomicOr(io.found, 1u);
     const uint64_t t1 = (flags & F_STATS) ? wall_clock64() : 0;
-    const uint32_t added = block_flush(st, io.nfq, io.ncnt, g.ends, io.ecnt, s_tmp);
+    const uint32_t added = block_flush(st, io.next, g.ends, io.ecnt, s_tmp, io.defer);
     if (threadIdx.x == 0) *ctr = 0;  // every wavefront is past it (the flush ends with a barrier)
     if (flags & F_STATS) { acc.tick(S_T_EXPAND, t1 - t0); acc.tick(S_T_FLUSH, wall_clock64() - t1); }
     return added;
@@ -496,6 +607,7 @@ DEV uint32_t expand_level(const DevGraph &g, const int4 *fq, uint32_t n, uint32_
 DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const RunOpt &o, uint32_t *cnt, Stage &st,
                     uint32_t *s_tmp, Acc &acc)
 {
+    const QSink q{g.fq0, cnt, nullptr, (o.flags & F_DEFER) != 0};
     const int lane = __lane_id();
     const uint32_t flags = o.flags;
     const uint32_t nc = (uint32_t)g.nc;
@@ -519,10 +631,10 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
             const int4 e = make_int4((int)c, (int)c, b[u], en[u]);
             if ((flags & F_LEVELS) && in) g.clevel[c] = un ? 0 : -1;
             if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
-            push_entry(p, e, o.split, st, g.fq0, cnt);
+            push_entry(p, e, o.split, st, q);
         }
     }
-    block_flush(st, g.fq0, cnt, g.ends, nullptr, s_tmp);
+    block_flush(st, q, g.ends, nullptr, s_tmp, false);
 }
 
 // Alternate (Algorithm 3) from every reached unmatched row, one thread per
@@ -659,12 +771,21 @@ DEV bool wait_release(uint32_t *ctrl, const uint64_t *wa, const uint64_t *wb, ui
 }
 
 // Release (thread 0): state B = {epoch, L | stop << 31} first, then
-// A = {epoch, n} with release order.
+// A = {epoch, n} with release order.  `light` (a barrier between two grid
+// levels whose shared data all travels in agent-scope atomics): no release
+// fence, only the completion of this thread's earlier stores (the counter
+// reset among them) before A; a reader that sees A before B goes round
+// again.
 DEV void release_state(uint64_t *wa, uint64_t *wb, uint32_t epoch, uint32_t L, uint32_t n, uint32_t stop,
-                       uint32_t *s_st)
+                       uint32_t *s_st, bool light = false)
 {
     __hip_atomic_store(wb, ((uint64_t)(L | stop << 31) << 32) | epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(wa, ((uint64_t)n << 32) | epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (light) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __hip_atomic_store(wa, ((uint64_t)n << 32) | epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(wa, ((uint64_t)n << 32) | epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
     s_st[0] = L;
     s_st[1] = n;
     s_st[2] = stop;
@@ -682,38 +803,74 @@ DEV void release_state(uint64_t *wa, uint64_t *wb, uint32_t epoch, uint32_t L, u
 //             the count returns the totals to the last block, which resets
 //             the counter for two epochs later and releases (one hop, one
 //             contended atomic per arriving block).
-template <class Touches>
+// The 64-bit counter of grid barrier epoch e (two, used alternately).
+DEV uint64_t *bar_counter(uint32_t *ctrl, uint32_t e)
+{
+    return reinterpret_cast<uint64_t *>(line(ctrl, (e & 1) ? L_BAR_CNT1 : L_BAR_CNT0));
+}
+
+// No deferred frontier writes.
+struct NoWrite {
+    DEV void operator()(uint32_t) const {}
+};
+
+// `defer`: after arriving, every thread of the workgroup calls write(base)
+// with the place that the counter addition returned for its staged
+// frontier entries (F_DEFER grid levels).
+template <class Touches, class Write = NoWrite>
 DEV bool grid_barrier(uint32_t *ctrl, uint32_t *bar, uint32_t &epoch, uint64_t timeout, int *s_ok, Grp gr,
                       uint32_t active, uint32_t idle_sleep, bool counter, const Pub &pub, uint32_t share,
-                      Touches touches, uint32_t *s_st, LvState *out)
+                      Touches touches, uint32_t *s_st, LvState *out, bool defer = false, Write write = NoWrite{})
 {
+    // deferred (counter barrier, F_DEFER grid level): everything the
+    // workgroup wrote for others went in agent-scope atomics, so the arrival
+    // needs no release fence (no L2 write-back), only the completion of
+    // every wavefront's stores; whether a waiter acquires is up to touches
+    if (defer) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     ++epoch;
     uint64_t *wa = reinterpret_cast<uint64_t *>(line(ctrl, L_BAR_GEN));
     uint64_t *wb = reinterpret_cast<uint64_t *>(line(ctrl, L_BAR_GEN) + 16);
     if (counter) {
+        // deferred: the low word of the counter also reserves the next
+        // frontier's slots (deferred blocks add their staged entries, and
+        // entries drained during the level were added before), so the value
+        // the addition returns is where this workgroup's staged entries go;
+        // they are written between the arrival and the wait
+        int ok = 1;
+        bool released = false;
         if (threadIdx.x == 0) {
-            int ok = status_of(ctrl) == 0;
+            ok = status_of(ctrl) == 0;
             s_st[3] = epoch;
-            bool released = false;
+            s_st[4] = 0;
             if (ok && gr.b < active) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                uint64_t *cnt = reinterpret_cast<uint64_t *>(line(ctrl, (epoch & 1) ? L_BAR_CNT1 : L_BAR_CNT0));
+                if (!defer) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                uint64_t *cnt = bar_counter(ctrl, epoch);
                 const uint64_t mine = (1ull << 48) | ((uint64_t)(share >> 31) << 32) | (share & 0x7fffffffu);
-                const uint64_t tot = __hip_atomic_fetch_add(cnt, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + mine;
+                const uint64_t prev = __hip_atomic_fetch_add(cnt, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t tot = prev + mine;
+                s_st[4] = (uint32_t)prev;
                 if ((uint32_t)(tot >> 48) == active) {
                     __hip_atomic_store(cnt, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    if (!defer) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     uint32_t n = pub.n_ptr ? ld_u<kAgent>(pub.n_ptr) : pub.n;
                     uint32_t stop = pub.stop_ptr ? (uint32_t)(ld_u<kAgent>(pub.stop_ptr) != 0) : pub.stop;
                     if (pub.sum) {
                         n = (uint32_t)(tot & 0xffffffffu);
                         stop = ((tot >> 32) & 0xffffu) != 0 ? 1u : 0u;
                     }
-                    release_state(wa, wb, epoch, pub.L, n, stop, s_st);
+                    release_state(wa, wb, epoch, pub.L, n, stop, s_st, defer);
+                    if (defer && touches(LvState{pub.L, n, stop})) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     released = true;
                 }
             }
+            s_st[5] = (uint32_t)ok;
+        }
+        if (defer) {
+            __syncthreads();
+            if (gr.b < active && s_st[5]) write(s_st[4]);
+        }
+        if (threadIdx.x == 0) {
             if (ok && !released) ok = wait_release(ctrl, wa, wb, epoch, timeout, gr.b < active, idle_sleep, touches, s_st);
             *s_ok = ok;
         }
@@ -817,8 +974,9 @@ DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uin
         __syncthreads();
         if (threadIdx.x == 0) { s_loc[(L + 2) % 3] = 0; s_loc[3] = 0; }
         __syncthreads();
-        const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
-        LevelIO io{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], &s_loc[4], &s_loc[3]};
+        int4 *cur = (L & 1) ? g.fq1 : g.fq0;
+        const LevelIO io{QSink{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], nullptr, (flags & F_DEFER) != 0},
+                         &s_loc[4], &s_loc[3], ctrl, false};
         expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
         ++levels;
         if ((flags & F_APSB) && *(volatile uint32_t *)&s_loc[3]) { stop = 1; break; }
@@ -856,19 +1014,26 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     // grid barrier (`active` blocks arrive; block 0 releases the loop state
     // `p` into s), with the time block 0 spends in it counted (stats=1)
     LvState s{0, 0, 0};
-    // does this block read shared data before its next barrier in state x?
-    // (it expands the level, or the level loop ends and Alternate follows)
+    const bool counter = (flags & F_BAR_COUNTER) != 0;
+    // F_DEFER: grid levels reserve their next frontier through the counter
+    // barrier, and all they share (queue entries, row words, pred, cdone,
+    // ends) goes through agent-scope atomics
+    const bool defer = counter && (flags & F_DEFER) != 0;
+    // does this block read data that others wrote with ordinary stores
+    // before its next barrier in state x? (it expands the level, or the
+    // level loop ends and Alternate follows; a deferred grid level reads
+    // nothing of the kind, so its L2 keeps the graph)
     auto in_level = [&](const LvState &x) -> bool {
         if (x.n == 0 || x.stop) return true;
         if (x.n <= o.small_max) return gr.b == 0;
+        if (defer) return false;
         return gr.b < level_blocks(x.n, o.level_entries, gr.n);
     };
     auto always = [](const LvState &) -> bool { return true; };
-    const bool counter = (flags & F_BAR_COUNTER) != 0;
-    auto sync = [&](uint32_t active, const Pub &p, uint32_t share) -> bool {
+    auto sync = [&](uint32_t active, const Pub &p, uint32_t share, bool dw, auto write) -> bool {
         const uint64_t t0 = timing ? wall_clock64() : 0;
         const bool ok = grid_barrier(ctrl, bar, epoch, o.timeout, s_ok, gr, active, o.idle_sleep, counter, p, share,
-                                     in_level, s_loc + 8, &s);
+                                     in_level, s_loc + 8, &s, dw, write);
         if (timing) acc.tick(S_T_BARRIER, wall_clock64() - t0);
         return ok;
     };
@@ -897,7 +1062,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
                     if (timing) acc.tick(S_T_SMALL, wall_clock64() - t0);
                     p = Pub{r.L, r.n, r.stop, nullptr, nullptr, false};
                 }
-                if (!sync(1, p, 0u)) return false;
+                if (!sync(1, p, 0u, false, NoWrite{})) return false;
                 continue;
             }
             const uint32_t active = level_blocks(s.n, o.level_entries, gr.n);
@@ -905,17 +1070,26 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             // this block's share of the next frontier (and, APsB, whether it
             // reached an unmatched row) rides on its arrival
             uint32_t share = 0;
+            // deferred: slots come from the counter of the barrier that ends
+            // this level (epoch + 1)
+            const QSink next{(L & 1) ? g.fq0 : g.fq1, fc((L + 1) % 3), defer ? bar_counter(ctrl, epoch + 1) : nullptr,
+                             defer};
             if (gr.b < active) {
-                const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
-                LevelIO io{(L & 1) ? g.fq0 : g.fq1, fc((L + 1) % 3), line(ctrl, L_NENDS), fd(L % 3)};
+                int4 *cur = (L & 1) ? g.fq1 : g.fq0;
+                const LevelIO io{next, line(ctrl, L_NENDS), fd(L % 3), ctrl, defer};
                 share = expand_level<WAVE, kAgent>(g, cur, s.n, wave, active * (blockDim.x >> 6), ph, L, o, io, st,
                                                    s_tmp, acc);
                 if (!(flags & F_APSB)) share &= 0x7fffffffu;
             }
             ++total_levels;
-            if (!sync(active, Pub{(uint32_t)L + 1, share & 0x7fffffffu, share >> 31, nullptr, nullptr, true}, share))
+            if (!sync(active, Pub{(uint32_t)L + 1, share & 0x7fffffffu, share >> 31, nullptr, nullptr, true}, share,
+                      defer, [&](uint32_t base) { write_deferred(st, next, base, s_tmp); }))
                 return false;
         }
+        // APsB stop: the frontier of level left.L (left.n entries) is never
+        // expanded; with deferred writes its slots are set back to -1 once
+        // they are certainly written (after the next grid barrier)
+        const LvState left = s;
         const uint32_t ne = ld_u<kAgent>(line(ctrl, L_NENDS));
         if (leader && timing && g.ptrace && ph <= (uint32_t)kPhaseTrace) {
             g.ptrace[2 * (ph - 1)] = total_levels - lv0;
@@ -926,6 +1100,10 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         alternate<kAgent>(g, ne, tid, nthreads, flags, ctrl, acc);
         if (!sync_all(none)) return false;
         fix_matching(g, tid, nthreads, flags, acc);
+        if ((flags & F_DEFER) && left.stop) {
+            const QSink lq{(left.L & 1) ? g.fq1 : g.fq0, nullptr, nullptr, true};
+            for (uint32_t i = tid; i < left.n; i += nthreads) put_entry(lq, i, make_int4(-1, -1, -1, -1));
+        }
         if (leader) {
             for (int i = 0; i < 3; ++i) { *fc(i) = 0; *fd(i) = 0; }
             *line(ctrl, L_NENDS) = 0;
@@ -960,8 +1138,9 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, Acc &acc,
             __syncthreads();
             if (threadIdx.x == 0) { s_loc[(L + 2) % 3] = 0; s_loc[3] = 0; }
             __syncthreads();
-            const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
-            LevelIO io{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], &s_loc[4], &s_loc[3]};
+            int4 *cur = (L & 1) ? g.fq1 : g.fq0;
+            const LevelIO io{QSink{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], nullptr, false}, &s_loc[4],
+                             &s_loc[3], ctrl, false};
             expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
             ++total_levels;
             if ((flags & F_APSB) && *(volatile uint32_t *)&s_loc[3]) break;
@@ -994,6 +1173,8 @@ __global__ void k_setup(DevGraph g, const int32_t *init_c, const int32_t *init_r
         g.cdone[c] = 0;
         if (flags & F_LEVELS) g.clevel[c] = -1;
     }
+    if (flags & F_DEFER)
+        for (uint64_t i = tid; i < 2 * g.qcap; i += nt) g.fq0[i] = make_int4(-1, -1, -1, -1);
     for (uint32_t r = tid; r < (uint32_t)g.nr; r += nt) {
         const int m = init_r ? init_r[r] : -1;
         g.rw[r] = (uint64_t)(uint32_t)m;
@@ -1038,7 +1219,7 @@ __global__ void __launch_bounds__(1024) k_persistent(DevGraph g, uint32_t *ctrl,
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_ok;
-    __shared__ uint32_t s_loc[12];
+    __shared__ uint32_t s_loc[16];  // [0..7] level counters, [8..13] barrier state
     __shared__ uint64_t s_acc[kAccN];
     Stage st = make_stage(smem);
     uint32_t *s_tmp = stage_tmp(smem);
@@ -1120,7 +1301,7 @@ __global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *desc
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_ok;
-    __shared__ uint32_t s_loc[12];
+    __shared__ uint32_t s_loc[16];  // [0..7] level counters, [8..13] barrier state
     __shared__ uint64_t s_acc[kAccN];
     const uint32_t q = blockIdx.x / group;
     const Grp gr{blockIdx.x % group, group};
@@ -1208,9 +1389,9 @@ __global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint
         *line(ctrl, L_FCOUNT0 + (L + 2) % 3) = 0;
         *line(ctrl, L_FOUND0 + (L + 2) % 3) = 0;
     }
-    const int4 *cur = (L & 1) ? g.fq1 : g.fq0;
-    LevelIO io{(L & 1) ? g.fq0 : g.fq1, line(ctrl, L_FCOUNT0 + (L + 1) % 3), line(ctrl, L_NENDS),
-               line(ctrl, L_FOUND0 + L % 3)};
+    int4 *cur = (L & 1) ? g.fq1 : g.fq0;
+    const LevelIO io{QSink{(L & 1) ? g.fq0 : g.fq1, line(ctrl, L_FCOUNT0 + (L + 1) % 3), nullptr, false},
+                     line(ctrl, L_NENDS), line(ctrl, L_FOUND0 + L % 3), ctrl, false};
     __shared__ uint64_t s_acc[kAccN];
     Acc acc = make_acc(s_acc, stage_tmp(smem));
     expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
@@ -1295,7 +1476,7 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
                                                    int64_t *card, uint32_t *ctrl, RunOpt o)
 {
     extern __shared__ __align__(16) char smem[];
-    __shared__ uint32_t s_loc[12];
+    __shared__ uint32_t s_loc[16];  // [0..7] level counters, [8..13] barrier state
     __shared__ int32_t s_next;
     __shared__ uint32_t s_m;
     __shared__ uint64_t s_acc[kAccN];

@@ -30,7 +30,7 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto", barrier="counter", claim="auto")
+                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto")
 
 
 @pytest.fixture(autouse=True)
@@ -215,6 +215,47 @@ def test_claim_modes(claim, combo, name):
     _set(wg_threshold=0, claim=claim, **combo)
     assert _gpu(g)[0] == _oracle_card(g), (claim, combo)
     assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (claim, combo)
+
+
+# Both ways of reserving a grid level's next frontier: a queue atomic per
+# workgroup, or the counter barrier's own addition with the entries written
+# after arriving (deferred).  Cases: APsB stops that leave a frontier behind
+# in a grid level (small_max 0) and in a single-workgroup run; every level
+# on all blocks; one block per entry; few blocks; R-MAT levels large enough
+# that wavefronts drain their stage during the level; cheap and empty starts.
+FLUSH_COMBOS = [dict(driver="apfb", mapping="wave", level_entries=128, small_max=256),
+                dict(driver="apsb", mapping="wave", level_entries=1, small_max=0),
+                dict(driver="apsb", mapping="thread", level_entries=128, small_max=256),
+                dict(driver="apfb", mapping="thread", level_entries=0, small_max=0),
+                dict(driver="apsb", mapping="wave", level_entries=4096, small_max=0, endpoints="all")]
+
+
+@pytest.mark.parametrize("flush", ["defer", "atomic"])
+@pytest.mark.parametrize("combo", FLUSH_COMBOS, ids=lambda c: "-".join(str(v) for v in c.values()))
+@pytest.mark.parametrize("name", ["uniform2000", "grid256p", "rmat15"])
+def test_flush_modes(flush, combo, name):
+    g = gg.workload(name)
+    _set(wg_threshold=0, loop="device", flush=flush, **combo)
+    assert _gpu(g)[0] == _oracle_card(g), (flush, combo)
+    assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (flush, combo)
+
+
+def test_deferred_levels_repeated():
+    """Many runs in a row on one workspace with deferred grid levels (queue
+    slots reused across levels, phases and runs; barriers between grid
+    levels without fences), varying the participating blocks and the
+    driver: every run equals the oracle's cardinality and is a valid
+    matching."""
+    for name in ("grid256p", "grid200", "rmat14"):
+        g = gg.workload(name)
+        ref = _oracle_card(g)
+        ref0 = _oracle_card(g, "empty")
+        for i in range(12):
+            _set(wg_threshold=0, loop="device", flush="defer", claim=("max", "probe")[i % 2],
+                 level_entries=(16, 128, 1024)[i % 3], driver=("apfb", "apsb")[(i // 3) % 2],
+                 small_max=(0, 256)[(i // 6) % 2])
+            assert _gpu(g, certify=False)[0] == ref, (name, i)
+            assert _gpu(g, "empty", certify=False)[0] == ref0, (name, i)
 
 
 # Grid levels with a varying number of participating blocks: every block
