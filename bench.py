@@ -210,6 +210,10 @@ def bench_phases(names, drivers=("apfb", "apsb")):
         _, cm0, rm0 = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)
         dg = mcm.to_device(g)
         icm, irm = torch.from_numpy(cm0).cuda(), torch.from_numpy(rm0).cuda()
+        # BFS levels in the paper's sense: no local levels (every level is
+        # one BFS layer and ends at a grid barrier)
+        local0 = mcm.get_option("local_levels")
+        mcm.set_option("local_levels", 0)
         for drv in drivers:
             mcm.set_option("driver", drv)
             mcm.set_option("stats", 1)
@@ -218,10 +222,12 @@ def bench_phases(names, drivers=("apfb", "apsb")):
             mcm.set_option("stats", 0)
             mcm.match(dg, icm, irm)
             ms = mcm.last_stats()["kernel_ms"]
-            rows.append({"workload": name, "driver": drv, "card": card, "ms": round(ms, 3), "phases": int(len(lv)),
+            rows.append({"workload": name, "driver": drv, "local_levels": 0, "card": card, "ms": round(ms, 3),
+                         "phases": int(len(lv)),
                          "levels": int(lv.sum()), "levels_max": int(lv.max()) if len(lv) else 0,
                          "levels_mean": round(float(lv.mean()), 1) if len(lv) else 0.0,
                          "levels_per_phase": lv.tolist(), "ends_per_phase": en.tolist()})
+        mcm.set_option("local_levels", local0)
     mcm.set_option("driver", "apfb")
     return rows
 

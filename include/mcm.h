@@ -328,6 +328,18 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              auto = defer when the graph
  *                                              has at most 8 edges per row
  *                                              on average
+ *   "local_levels" "6" (default) | "0".."16"   levels of the persistent
+ *                                              loop: a wavefront expands the
+ *                                              columns it has just reached
+ *                                              (its newest 64 staged entries)
+ *                                              up to this many times more
+ *                                              before the grid barrier, so a
+ *                                              barrier covers several BFS
+ *                                              layers of such chains; 0 =
+ *                                              strictly level-synchronous as
+ *                                              in Algorithm 1 (BFS trees are
+ *                                              then shortest-path trees; the
+ *                                              matching is maximum either way)
  *   "validate"  "0" (default) | "1"            check CSC and init on device
  *   "stats"     "0" (default) | "1"            count scanned edges etc.
  *   "tuning"    path of an autotuner cache file (JSON lines) or ""

@@ -194,6 +194,7 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     r.split = (uint32_t)o.split;
     r.level_entries = (uint32_t)o.level_entries;
     r.idle_sleep = (uint32_t)o.idle_sleep;
+    r.local_levels = (uint32_t)o.local_levels;
     r.timeout = (uint64_t)(o.timeout_s * info.clock_khz * 1000.0);
     return r;
 }
@@ -480,6 +481,9 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "one") g_opt.endpoints = 1;
         else if (v == "auto") g_opt.endpoints = 2;
         else return (int)fail(MCM_EINVAL, "endpoints must be all, one or auto");
+    } else if (k == "local_levels") {
+        if (!as_int(0, 16, &x)) return (int)fail(MCM_EINVAL, "local_levels must be in [0, 16]");
+        g_opt.local_levels = (int)x;
     } else if (k == "flush") {
         if (v == "atomic") g_opt.flush = 0;
         else if (v == "defer") g_opt.flush = 1;
@@ -550,6 +554,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "endpoints") v = o.endpoints == 0 ? "all" : (o.endpoints == 1 ? "one" : "auto");
     else if (k == "claim") v = o.claim == 0 ? "probe" : (o.claim == 1 ? "max" : "auto");
     else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
+    else if (k == "local_levels") v = std::to_string(o.local_levels);
     else if (k == "multi_group") v = std::to_string(o.multi_group);
     else if (k == "batch_min") v = std::to_string(o.batch_min);
     else if (k == "split") v = std::to_string(o.split);

@@ -61,6 +61,7 @@ struct Options {
     int endpoints = 2;        // WR path ends per root: 0 all reached, 1 the first only, 2 auto (1 for APsB)
     int claim = 2;            // row claim: 0 probe + compare-and-swap, 1 atomic maximum, 2 auto (by degree)
     int flush = 2;            // grid levels: 0 reserve by a queue atomic, 1 through the counter barrier, 2 auto (1)
+    int local_levels = 6;     // grid levels: a wavefront expands its own new entries this many times more
     int mapping = 2;          // 0 thread, 1 wave, 2 auto
     int loop = 2;             // 0 device, 1 host, 2 auto
     bool validate = false;

@@ -84,6 +84,8 @@ struct RunOpt {
     uint32_t level_entries;  // grid levels: one block per this many frontier entries takes part
                              // (the rest wait for the level's end); 0 = every block, every level
     uint32_t idle_sleep;   // polls of a barrier waiter that did not arrive are this many s_sleep(1) apart
+    uint32_t local_levels; // grid levels: times a wavefront expands its own newest entries before the
+                           // level ends (0 = strictly level-synchronous)
     uint64_t timeout;      // wall-clock ticks a grid barrier may wait
 };
 

@@ -485,7 +485,8 @@ DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, const QSin
 
 template <bool WAVE, int S>
 DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
-                          int level, const RunOpt &o, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc)
+                          int level, const RunOpt &o, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc,
+                          uint32_t local = 0)
 {
     const int lane = __lane_id();
     const uint32_t flags = o.flags;
@@ -506,14 +507,11 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
     const uint32_t wpb = blockDim.x >> 6, blk = wave / wpb, nblk = nwaves / wpb;
     const bool dyn = (uint64_t)nwaves * B < n;
     uint32_t *ctr = s_tmp + kBatchCtr;
-    // one batch of entries [base, base + B) of the frontier
-    auto batch = [&](const uint32_t base) {
-        const uint32_t i = base + lane;
-        int4 e = make_int4(0, 0, 0, 0);
+    // expand one entry per lane (lanes with `have`)
+    auto expand = [&](const int4 e, const bool have) {
         int deg = 0;
         uint32_t rdone = 0;
-        if ((uint32_t)lane < B && i < n) {
-            e = io.next.atomic ? take_entry(fq, i, io.ctrl, o.timeout) : fq[i];
+        if (have) {
             deg = e.w - e.z;
             if (late) rdone = ld_u<S>(&g.cdone[e.y]);
             else if ((flags & F_WR) && deg > 0 && ld_u<S>(&g.cdone[e.y]) == ph) deg = 0;
@@ -578,7 +576,15 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
                 }
             }
         }
-        };
+    };
+    // one batch of entries [base, base + B) of the frontier
+    auto batch = [&](const uint32_t base) {
+        const uint32_t i = base + lane;
+        const bool have = (uint32_t)lane < B && i < n;
+        int4 e = make_int4(0, 0, 0, 0);
+        if (have) e = io.next.atomic ? take_entry(fq, i, io.ctrl, o.timeout) : fq[i];
+        expand(e, have);
+    };
     if (dyn) {
         for (;;) {
             uint32_t k = 0;
@@ -590,6 +596,22 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
         }
     } else if (wave * B < n) {
         batch(wave * B);
+        // Local levels: the wavefront expands the newest entries it staged
+        // (at most 64) itself, up to `local` times, before the level ends.
+        // Every claim is still made once, from a column whose row was
+        // claimed in the same tree, so the trees stay alternating BFS
+        // trees; a column expanded this way is one level early for its tree
+        // (levels are then no longer exact, so level-set runs pass 0).
+        for (uint32_t k = 0; k < local; ++k) {
+            const int m = st.nq < 64 ? st.nq : 64;
+            if (m == 0) break;
+            wave_lds_sync();
+            const bool have = lane < m;
+            const int4 e = have ? st.q[st.nq - m + lane] : make_int4(0, 0, 0, 0);
+            wave_lds_sync();
+            st.nq -= m;
+            expand(e, have);
+        }
     }
     if ((flags & F_APSB) && __ballot(any_end) != 0 && lane == 0) atomicOr(io.found, 1u);
     const uint64_t t1 = (flags & F_STATS) ? wall_clock64() : 0;
@@ -1078,7 +1100,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
                 int4 *cur = (L & 1) ? g.fq1 : g.fq0;
                 const LevelIO io{next, line(ctrl, L_NENDS), fd(L % 3), ctrl, defer};
                 share = expand_level<WAVE, kAgent>(g, cur, s.n, wave, active * (blockDim.x >> 6), ph, L, o, io, st,
-                                                   s_tmp, acc);
+                                                   s_tmp, acc, (flags & F_LEVELS) ? 0u : o.local_levels);
                 if (!(flags & F_APSB)) share &= 0x7fffffffu;
             }
             ++total_levels;

@@ -30,7 +30,7 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto")
+                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels=6)
 
 
 @pytest.fixture(autouse=True)
@@ -238,6 +238,26 @@ def test_flush_modes(flush, combo, name):
     _set(wg_threshold=0, loop="device", flush=flush, **combo)
     assert _gpu(g)[0] == _oracle_card(g), (flush, combo)
     assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (flush, combo)
+
+
+# Local levels: a wavefront expands the entries it just claimed before the
+# grid level ends (the trees are no longer level-exact, the cardinality is
+# still the oracle's).  Both mappings and drivers, both flush forms, both
+# claims, APsB stops in a local level.
+LOCAL_COMBOS = [dict(driver="apfb", mapping="wave", flush="defer", claim="max"),
+                dict(driver="apsb", mapping="wave", flush="defer", claim="probe"),
+                dict(driver="apfb", mapping="thread", flush="atomic", claim="probe"),
+                dict(driver="apsb", mapping="thread", flush="atomic", claim="max", endpoints="all")]
+
+
+@pytest.mark.parametrize("local", [0, 1, 3, 16])
+@pytest.mark.parametrize("combo", LOCAL_COMBOS, ids=lambda c: "-".join(str(v) for v in c.values()))
+@pytest.mark.parametrize("name", ["uniform2000", "grid256p", "rmat15"])
+def test_local_levels(local, combo, name):
+    g = gg.workload(name)
+    _set(wg_threshold=0, loop="device", small_max=0, local_levels=local, **combo)
+    assert _gpu(g)[0] == _oracle_card(g), (local, combo)
+    assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (local, combo)
 
 
 def test_deferred_levels_repeated():
