@@ -110,6 +110,23 @@ DEV uint64_t wave_sum(uint64_t x)
 
 DEV uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
+// Add v, summed over the workgroup, to *dst with one atomic per workgroup
+// (same-address atomics serialise, ~11 ns each; one per wavefront of a
+// large grid costs a fifth of a millisecond).  Every thread calls it.
+DEV void block_add(uint64_t v, uint64_t *dst)
+{
+    __shared__ uint64_t s_part[16];
+    v = wave_sum(v);
+    if (__lane_id() == 0) s_part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) t += s_part[w];
+        if (t) atomicAdd((unsigned long long *)dst, (unsigned long long)t);
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------
 // Per-wavefront staging of queue pushes.
 struct Stage {
@@ -1376,8 +1393,7 @@ __global__ void k_finish_multi(const BatchDesc *descs, int32_t ngraphs, int64_t 
         for (uint32_t r = tid; r < (uint32_t)d.nr; r += nt) d.out_r[r] = (int32_t)(uint32_t)d.rw[r];
         uint64_t m = 0;
         for (uint32_t c = tid; c < (uint32_t)d.nc; c += nt) m += (d.out_c[c] >= 0);
-        m = wave_sum(m);
-        if (__lane_id() == 0 && m) atomicAdd((unsigned long long *)&card[gi], (unsigned long long)m);
+        block_add(m, reinterpret_cast<uint64_t *>(&card[gi]));
     }
 }
 
@@ -1449,8 +1465,7 @@ __global__ void k_finish(DevGraph g, int32_t *out_r, uint32_t *ctrl)
     for (uint32_t r = tid; r < (uint32_t)g.nr; r += nt) out_r[r] = (int32_t)(uint32_t)g.rw[r];
     uint64_t m = 0;
     for (uint32_t c = tid; c < (uint32_t)g.nc; c += nt) m += (g.cmatch[c] >= 0);
-    m = wave_sum(m);
-    if (__lane_id() == 0 && m) atomicAdd((unsigned long long *)line(ctrl, L_CARD), (unsigned long long)m);
+    block_add(m, reinterpret_cast<uint64_t *>(line(ctrl, L_CARD)));
 }
 
 // Konig cover from the state left by one complete BFS phase (stamp ph):
@@ -1471,8 +1486,7 @@ __global__ void k_cover(DevGraph g, uint32_t ph, uint8_t *col_cov, uint8_t *row_
         row_cov[r] = v;
         k += v;
     }
-    k = wave_sum(k);
-    if (__lane_id() == 0 && k) atomicAdd((unsigned long long *)line(ctrl, L_CARD), (unsigned long long)k);
+    block_add(k, reinterpret_cast<uint64_t *>(line(ctrl, L_CARD)));
 }
 
 // pred of reached rows for the level inspection entry point
@@ -1688,14 +1702,14 @@ hipError_t launch_fix(const DevGraph &g, uint32_t *ctrl, uint32_t flags, hipStre
 hipError_t launch_finish(const DevGraph &g, int32_t *out_r, uint32_t *ctrl, hipStream_t st)
 {
     const int64_t n = g.nc > g.nr ? g.nc : g.nr;
-    hipLaunchKernelGGL(k_finish, dim3(clamp_blocks(n, 256, 1, 4096)), dim3(256), 0, st, g, out_r, ctrl);
+    hipLaunchKernelGGL(k_finish, dim3(clamp_blocks(n, 2048, 1, 1024)), dim3(256), 0, st, g, out_r, ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_cover(const DevGraph &g, uint32_t ph, uint8_t *cc, uint8_t *rc, uint32_t *ctrl, hipStream_t st)
 {
     const int64_t n = g.nc > g.nr ? g.nc : g.nr;
-    hipLaunchKernelGGL(k_cover, dim3(clamp_blocks(n, 256, 1, 4096)), dim3(256), 0, st, g, ph, cc, rc, ctrl);
+    hipLaunchKernelGGL(k_cover, dim3(clamp_blocks(n, 2048, 1, 1024)), dim3(256), 0, st, g, ph, cc, rc, ctrl);
     return hipGetLastError();
 }
 
