@@ -394,7 +394,10 @@ typedef struct {
     int32_t loop;            /* 0 = device-side level loop, 1 = host-side */
     int32_t mapping;         /* 0 = thread, 1 = wave */
     int64_t claims_tried;    /* compare-and-swaps on rows the probe saw unreached (stats=1);
-                                claims_tried - cols_claimed - rows_found were lost to another lane */
+                                claims_tried - cols_claimed - rows_found were lost to another lane;
+                                with claim = max: atomic maxima on rows not yet stamped */
+    int32_t claim;           /* row claims used: 0 = probe + compare-and-swap, 1 = atomic maximum */
+    int32_t flush;           /* grid levels: 0 = queue atomic, 1 = deferred (counter barrier) */
 } mcm_stats;
 
 int mcm_last_stats(mcm_stats *out);

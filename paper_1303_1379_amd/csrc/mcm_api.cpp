@@ -326,6 +326,8 @@ void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int l
     s.kernel_ms = ms;
     s.loop = loop;
     s.mapping = (flags & F_WAVE) ? 1 : 0;
+    s.claim = (flags & F_MAXCLAIM) ? 1 : 0;
+    s.flush = (flags & F_DEFER) && loop == 0 ? 1 : 0;
     g_stats = s;
 }
 

@@ -260,6 +260,26 @@ def test_local_levels(local, combo, name):
     assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (local, combo)
 
 
+@pytest.mark.parametrize("name,low", [("grid256p", True), ("uniform2000", True), ("rmat15", False)])
+def test_auto_claim_and_flush(name, low):
+    """claim=auto and flush=auto pick the atomic maximum and deferred levels
+    for graphs with at most 8 edges per row on average, the probe and the
+    queue atomic otherwise; deferred levels need the device loop and the
+    counter barrier."""
+    g = gg.workload(name)
+    ref = _oracle_card(g)
+    _set(wg_threshold=0)
+    assert _gpu(g, certify=False)[0] == ref
+    s = mcm.last_stats()
+    assert (s["claim"], s["flush"]) == ((1, 1) if low else (0, 0))
+    _set(loop="host")
+    assert _gpu(g, certify=False)[0] == ref
+    assert mcm.last_stats()["flush"] == 0
+    _set(loop="device", barrier="flags")
+    assert _gpu(g, certify=False)[0] == ref
+    assert mcm.last_stats()["flush"] == 0
+
+
 def test_deferred_levels_repeated():
     """Many runs in a row on one workspace with deferred grid levels (queue
     slots reused across levels, phases and runs; barriers between grid
