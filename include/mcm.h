@@ -328,8 +328,11 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              auto = defer when the graph
  *                                              has at most 8 edges per row
  *                                              on average
- *   "local_levels" "6" (default) | "0".."16"   levels of the persistent
- *                                              loop: a wavefront expands the
+ *   "local_levels" "6" (default) | "0".."16"   levels of mcm_match's
+ *                                              persistent loop (not the
+ *                                              multi-graph launch of
+ *                                              batches and the server): a
+ *                                              wavefront expands the
  *                                              columns it has just reached
  *                                              (its newest 64 staged entries)
  *                                              up to this many times more

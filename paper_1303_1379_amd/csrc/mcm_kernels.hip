@@ -1036,7 +1036,10 @@ DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uin
 }
 
 // The phase loop of Algorithm 1 over the whole grid (cooperative launch).
-template <bool WAVE>
+// LOCAL: local levels (option local_levels) in this launch.  Off in the
+// multi-graph launch, where they lengthened the serving latency (p50 45 ->
+// 50 ms at 2000 requests/s) and cost registers.
+template <bool WAVE, bool LOCAL = true>
 DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt &o, uint64_t *stats, Acc &acc, Stage &st,
                   uint32_t *s_tmp, uint32_t *s_loc, int *s_ok, uint32_t *ph_out, uint32_t *lv_out, Grp gr,
                   uint32_t &epoch)
@@ -1117,7 +1120,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
                 int4 *cur = (L & 1) ? g.fq1 : g.fq0;
                 const LevelIO io{next, line(ctrl, L_NENDS), fd(L % 3), ctrl, defer};
                 share = expand_level<WAVE, kAgent>(g, cur, s.n, wave, active * (blockDim.x >> 6), ph, L, o, io, st,
-                                                   s_tmp, acc, (flags & F_LEVELS) ? 0u : o.local_levels);
+                                                   s_tmp, acc, (!LOCAL || (flags & F_LEVELS)) ? 0u : o.local_levels);
                 if (!(flags & F_APSB)) share &= 0x7fffffffu;
             }
             ++total_levels;
@@ -1374,7 +1377,7 @@ __global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *desc
         if (d.nc > 0 && d.nr > 0) {
             DevGraph g = graph_of(d);
             uint32_t ph = 0, lv = 0;
-            ok = run_grid<WAVE>(g, ctrl, bar, o, stats, acc, st, s_tmp, s_loc, &s_ok, &ph, &lv, gr, epoch);
+            ok = run_grid<WAVE, false>(g, ctrl, bar, o, stats, acc, st, s_tmp, s_loc, &s_ok, &ph, &lv, gr, epoch);
         }
         if (!ok) return;                      // watchdog: this graph and the group stop
         if (leader) card[gi] = kGraphDone;    // k_finish_multi counts |M| on top
