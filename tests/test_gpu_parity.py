@@ -432,6 +432,22 @@ def test_full_size_certified(name):
         assert n - int((dc | dr).sum()) <= card <= n - nd
 
 
+@pytest.mark.parametrize("opts", [dict(claim="probe", flush="atomic", local_levels=0),
+                                  dict(claim="max", flush="defer", local_levels=0),
+                                  dict(claim="probe", flush="defer", local_levels=16)],
+                         ids=lambda d: "-".join(str(v) for v in d.values()))
+@pytest.mark.parametrize("name", ["grid2048", "rmat23"])
+def test_full_size_other_forms(name, opts):
+    """The full-size workloads with the claim, flush and local-level forms
+    that the defaults do not pick for them: a valid matching certified
+    maximum by the GPU's Konig cover, the same size as with the defaults."""
+    g = gg.workload(name)
+    ref, _, _ = _gpu(g)
+    _set(**opts)
+    card, _, _ = _gpu(g)
+    assert card == ref, opts
+
+
 @pytest.mark.parametrize("loop", ["device", "host"])
 @pytest.mark.parametrize("name,driver", [("grid256", "apfb"), ("grid256p", "apfb"), ("rmat14", "apsb")])
 def test_phase_record(name, driver, loop):
