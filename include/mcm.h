@@ -328,6 +328,16 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              auto = defer when the graph
  *                                              has at most 8 edges per row
  *                                              on average
+ *   "wr_check"  "auto" (default) | "early" | "late"
+ *                                              where GPUBFS-WR tests whether
+ *                                              an entry's root already has a
+ *                                              path (wave mapping): before
+ *                                              the entry's edges are read,
+ *                                              or beside each edge visit;
+ *                                              auto = late for graphs with
+ *                                              at most 8 edges per row on
+ *                                              average, early otherwise
+ *                                              (late outside mcm_match)
  *   "local_levels" "6" (default) | "0".."16"   levels of mcm_match's
  *                                              persistent loop (not the
  *                                              multi-graph launch of
@@ -349,7 +359,7 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *   "autotune"  "0" (default) | "1"            batch plans time candidates
  *   "block", "blocks_per_cu", "wg_block", "wg_threshold", "small_max",
  *   "batch_min", "split", "timeout_s", "max_blocks", "level_entries",
- *   "idle_sleep", "wr_check", "barrier", "multi_threshold", "multi_group"
+ *   "idle_sleep", "barrier", "multi_threshold", "multi_group"
  *                                              launch-shape details (see
  *                                              the host driver)
  * Return MCM_OK or MCM_EINVAL (unknown key or value).  mcm_get_option
@@ -401,6 +411,7 @@ typedef struct {
                                 with claim = max: atomic maxima on rows not yet stamped */
     int32_t claim;           /* row claims used: 0 = probe + compare-and-swap, 1 = atomic maximum */
     int32_t flush;           /* grid levels: 0 = queue atomic, 1 = deferred (counter barrier) */
+    int32_t wr_check;        /* GPUBFS-WR root test: 0 = before the scan, 1 = beside each edge visit */
 } mcm_stats;
 
 int mcm_last_stats(mcm_stats *out);

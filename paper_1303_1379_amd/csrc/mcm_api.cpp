@@ -277,7 +277,7 @@ uint32_t base_flags(const Options &o, int64_t nc, int64_t nnz_hint)
 {
     uint32_t f = 0;
     if (o.wr) f |= F_WR;
-    if (o.wr_late) f |= F_WR_LATE;
+    if (o.wr_check != 0) f |= F_WR_LATE;
     if (o.bar_counter) f |= F_BAR_COUNTER;
     if (o.endpoints == 1 || (o.endpoints == 2 && o.apsb)) f |= F_ENDPOINT;
     if (o.apsb) f |= F_APSB;
@@ -328,6 +328,7 @@ void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int l
     s.mapping = (flags & F_WAVE) ? 1 : 0;
     s.claim = (flags & F_MAXCLAIM) ? 1 : 0;
     s.flush = (flags & F_DEFER) && loop == 0 ? 1 : 0;
+    s.wr_check = (flags & F_WR_LATE) ? 1 : 0;
     g_stats = s;
 }
 
@@ -501,9 +502,10 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "counter") g_opt.bar_counter = true;
         else return (int)fail(MCM_EINVAL, "barrier must be flags or counter");
     } else if (k == "wr_check") {
-        if (v == "late") g_opt.wr_late = true;
-        else if (v == "early") g_opt.wr_late = false;
-        else return (int)fail(MCM_EINVAL, "wr_check must be early or late");
+        if (v == "late") g_opt.wr_check = 1;
+        else if (v == "early") g_opt.wr_check = 0;
+        else if (v == "auto") g_opt.wr_check = 2;
+        else return (int)fail(MCM_EINVAL, "wr_check must be early, late or auto");
     } else if (k == "idle_sleep") {
         if (!as_int(0, 4096, &x)) return (int)fail(MCM_EINVAL, "idle_sleep must be in [0, 4096]");
         g_opt.idle_sleep = (int)x;
@@ -551,7 +553,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "multi_threshold") v = std::to_string(o.multi_threshold);
     else if (k == "level_entries") v = std::to_string(o.level_entries);
     else if (k == "idle_sleep") v = std::to_string(o.idle_sleep);
-    else if (k == "wr_check") v = o.wr_late ? "late" : "early";
+    else if (k == "wr_check") v = o.wr_check == 0 ? "early" : (o.wr_check == 1 ? "late" : "auto");
     else if (k == "barrier") v = o.bar_counter ? "counter" : "flags";
     else if (k == "endpoints") v = o.endpoints == 0 ? "all" : (o.endpoints == 1 ? "one" : "auto");
     else if (k == "claim") v = o.claim == 0 ? "probe" : (o.claim == 1 ? "max" : "auto");
@@ -638,7 +640,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     size_t qcap = 0;
     int64_t nnz = -1;
     if ((rc = queue_capacity(ncols, colptr, single_wg ? 0u : (uint32_t)o.split, st, &qcap,
-                             single_wg || (o.claim != 2 && o.flush != 2) ? nullptr : &nnz)))
+                             single_wg || (o.claim != 2 && o.flush != 2 && o.wr_check != 2) ? nullptr : &nnz)))
         return rc;
     if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows, std::max(qcap, (size_t)ncols)))) return rc;
 
@@ -659,6 +661,11 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     // all but the first visitor of a level skip the atomic.
     const bool low_degree = nnz >= 0 && nnz <= kMaxClaimDegree * (int64_t)nrows;
     if (!single_wg && (o.claim == 1 || (o.claim == 2 && low_degree))) flags |= F_MAXCLAIM;
+    // The WR root check: beside the edge visit on low-degree graphs (their
+    // long chains of small levels would wait for the root's load before the
+    // scan), before the scan on skewed ones (their large levels save the
+    // rowind loads of trees that are done).
+    if (!single_wg && o.wr_check == 2 && !low_degree) flags &= ~(uint32_t)F_WR_LATE;
     // Persistent level loop with the counter barrier: a grid level's next
     // frontier is reserved by the barrier's own addition, and grid levels
     // pass their barriers without fences (what they share is in agent-scope

@@ -57,7 +57,8 @@ const std::string &last_error();
 struct Options {
     bool apsb = false;        // driver
     bool wr = true;           // bfs
-    bool wr_late = true;      // WR root check beside the edge visit (wave mapping)
+    int wr_check = 2;         // WR root check (wave mapping): 0 before the scan, 1 beside the edge visit,
+                              // 2 auto (mcm_match: beside on low-degree graphs, before otherwise; 1 elsewhere)
     int endpoints = 2;        // WR path ends per root: 0 all reached, 1 the first only, 2 auto (1 for APsB)
     int claim = 2;            // row claim: 0 probe + compare-and-swap, 1 atomic maximum, 2 auto (by degree)
     int flush = 2;            // grid levels: 0 reserve by a queue atomic, 1 through the counter barrier, 2 auto (1)

@@ -37,7 +37,7 @@ def test_version_and_strerror():
 def test_options_roundtrip_and_rejects():
     for k, v in [("driver", "apsb"), ("bfs", "plain"), ("mapping", "thread"), ("loop", "host"),
                  ("validate", "1"), ("stats", "1"), ("block", "512"), ("wg_threshold", "100"),
-                 ("level_entries", "0"), ("idle_sleep", "32"), ("wr_check", "early"), ("multi_threshold", "0"),
+                 ("level_entries", "0"), ("idle_sleep", "32"), ("wr_check", "early"), ("wr_check", "late"), ("multi_threshold", "0"),
                  ("multi_group", "8"), ("max_blocks", "32"), ("endpoints", "one"), ("barrier", "counter"),
                  ("claim", "max"), ("claim", "probe"), ("flush", "atomic"), ("flush", "defer"),
                  ("local_levels", "2")]:

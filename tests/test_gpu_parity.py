@@ -30,7 +30,7 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="late", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels=6)
+                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels=6)
 
 
 @pytest.fixture(autouse=True)
@@ -262,16 +262,17 @@ def test_local_levels(local, combo, name):
 
 @pytest.mark.parametrize("name,low", [("grid256p", True), ("uniform2000", True), ("rmat15", False)])
 def test_auto_claim_and_flush(name, low):
-    """claim=auto and flush=auto pick the atomic maximum and deferred levels
-    for graphs with at most 8 edges per row on average, the probe and the
-    queue atomic otherwise; deferred levels need the device loop and the
+    """claim, flush and wr_check on auto pick the atomic maximum, deferred
+    levels and the root test beside the edge visit for graphs with at most 8
+    edges per row on average, the probe, the queue atomic and the root test
+    before the scan otherwise; deferred levels need the device loop and the
     counter barrier."""
     g = gg.workload(name)
     ref = _oracle_card(g)
     _set(wg_threshold=0)
     assert _gpu(g, certify=False)[0] == ref
     s = mcm.last_stats()
-    assert (s["claim"], s["flush"]) == ((1, 1) if low else (0, 0))
+    assert (s["claim"], s["flush"], s["wr_check"]) == ((1, 1, 1) if low else (0, 0, 0))
     _set(loop="host")
     assert _gpu(g, certify=False)[0] == ref
     assert mcm.last_stats()["flush"] == 0
