@@ -406,7 +406,8 @@ def main():
                    "bfs": mcm.get_option("bfs"), "mapping": mcm.get_option("mapping"),
                    "loop": mcm.get_option("loop"), "claim": ("probe", "max")[last["claim"]],
                    "flush": ("atomic", "defer")[last["flush"]], "wr_check": ("early", "late")[last["wr_check"]],
-                   "local_levels": int(mcm.get_option("local_levels"))},
+                   "local_levels": int(mcm.get_option("local_levels")),
+                   "alternate": ("classic", "fast")[last["alternate"]]},
         "card": cards[0],
         "init_card": int(init_card),
         "matching_ms_median": round(float(np.median(kernel_ms)), 4),

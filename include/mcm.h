@@ -338,6 +338,22 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              at most 8 edges per row on
  *                                              average, early otherwise
  *                                              (late outside mcm_match)
+ *   "alternate" "auto" (default) | "fast" | "classic"
+ *                                              mcm_match's Alternate
+ *                                              (Algorithm 3): a claim also
+ *                                              records the row that held the
+ *                                              claiming column, so a walk
+ *                                              step loads pred and that row
+ *                                              together (fast; walks that
+ *                                              share a way to the root flip
+ *                                              it alike and FixMatching
+ *                                              settles their junction), or
+ *                                              reads cmatch after pred and
+ *                                              stops where another walk
+ *                                              passed (classic, as printed);
+ *                                              auto = fast for graphs with
+ *                                              at most 8 edges per row on
+ *                                              average, classic otherwise
  *   "local_levels" "6" (default) | "0".."16"   levels of mcm_match's
  *                                              persistent loop (not the
  *                                              multi-graph launch of
@@ -412,6 +428,7 @@ typedef struct {
     int32_t claim;           /* row claims used: 0 = probe + compare-and-swap, 1 = atomic maximum */
     int32_t flush;           /* grid levels: 0 = queue atomic, 1 = deferred (counter barrier) */
     int32_t wr_check;        /* GPUBFS-WR root test: 0 = before the scan, 1 = beside each edge visit */
+    int32_t alternate;       /* Alternate: 0 = classic, 1 = along the rows recorded at the claims */
 } mcm_stats;
 
 int mcm_last_stats(mcm_stats *out);

@@ -141,6 +141,21 @@ static int64_t ensure_radj(Workspace &w, size_t nr)
     return 0;
 }
 
+// Rows recorded by the claims for nr rows (alternate=fast only).
+static int64_t ensure_prow(Workspace &w, size_t nr)
+{
+    if (nr <= w.cap_prow) return 0;
+    free_dev(w.prow);
+    w.prow = nullptr;
+    const size_t cap = std::max(nr, w.cap_prow + w.cap_prow / 2);
+    if (hipMalloc(&w.prow, sizeof(int32_t) * cap) != hipSuccess) {
+        w.cap_prow = 0;
+        return fail(MCM_ENOMEM, "workspace allocation for %zu recorded rows failed", nr);
+    }
+    w.cap_prow = cap;
+    return 0;
+}
+
 int64_t ensure_desc(Workspace &w, size_t n)
 {
     if (n <= w.cap_desc) return 0;
@@ -329,6 +344,7 @@ void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int l
     s.claim = (flags & F_MAXCLAIM) ? 1 : 0;
     s.flush = (flags & F_DEFER) && loop == 0 ? 1 : 0;
     s.wr_check = (flags & F_WR_LATE) ? 1 : 0;
+    s.alternate = (flags & F_FASTALT) ? 1 : 0;
     g_stats = s;
 }
 
@@ -484,6 +500,11 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "one") g_opt.endpoints = 1;
         else if (v == "auto") g_opt.endpoints = 2;
         else return (int)fail(MCM_EINVAL, "endpoints must be all, one or auto");
+    } else if (k == "alternate") {
+        if (v == "fast") g_opt.alternate = 1;
+        else if (v == "classic") g_opt.alternate = 0;
+        else if (v == "auto") g_opt.alternate = 2;
+        else return (int)fail(MCM_EINVAL, "alternate must be fast, classic or auto");
     } else if (k == "local_levels") {
         if (!as_int(0, 16, &x)) return (int)fail(MCM_EINVAL, "local_levels must be in [0, 16]");
         g_opt.local_levels = (int)x;
@@ -559,6 +580,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "claim") v = o.claim == 0 ? "probe" : (o.claim == 1 ? "max" : "auto");
     else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
     else if (k == "local_levels") v = std::to_string(o.local_levels);
+    else if (k == "alternate") v = o.alternate == 0 ? "classic" : (o.alternate == 1 ? "fast" : "auto");
     else if (k == "multi_group") v = std::to_string(o.multi_group);
     else if (k == "batch_min") v = std::to_string(o.batch_min);
     else if (k == "split") v = std::to_string(o.split);
@@ -640,7 +662,9 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     size_t qcap = 0;
     int64_t nnz = -1;
     if ((rc = queue_capacity(ncols, colptr, single_wg ? 0u : (uint32_t)o.split, st, &qcap,
-                             single_wg || (o.claim != 2 && o.flush != 2 && o.wr_check != 2) ? nullptr : &nnz)))
+                             single_wg || (o.claim != 2 && o.flush != 2 && o.wr_check != 2 && o.alternate != 2)
+                                 ? nullptr
+                                 : &nnz)))
         return rc;
     if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows, std::max(qcap, (size_t)ncols)))) return rc;
 
@@ -709,6 +733,14 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
         g.radj = w.radj;
     }
     g.qcap = w.cap_q;
+    // Alternate along recorded rows where walks are long (low-degree graphs:
+    // grid2048 430 -> 413 ms); on skewed graphs the extra load per entry
+    // and store per claim cost more than their short walks save.
+    if (o.alternate == 1 || (o.alternate == 2 && low_degree)) {
+        if ((rc = ensure_prow(w, (size_t)nrows))) return rc;
+        g.prow = w.prow;
+        flags |= F_FASTALT;
+    }
     HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, w.bar, flags, st));
     if ((rc = run_graph(w, o, g, flags, st, &loop))) return rc;
     HIPCHK(launch_finish(g, out_rmatch, w.ctrl, st));

@@ -63,6 +63,7 @@ struct Options {
     int claim = 2;            // row claim: 0 probe + compare-and-swap, 1 atomic maximum, 2 auto (by degree)
     int flush = 2;            // grid levels: 0 reserve by a queue atomic, 1 through the counter barrier, 2 auto (1)
     int local_levels = 6;     // grid levels: a wavefront expands its own new entries this many times more
+    int alternate = 2;        // mcm_match's Alternate: 0 classic, 1 recorded rows, 2 auto (1 on low degree)
     int mapping = 2;          // 0 thread, 1 wave, 2 auto
     int loop = 2;             // 0 device, 1 host, 2 auto
     bool validate = false;
@@ -103,6 +104,8 @@ struct Workspace {
     int32_t *ends = nullptr;
     int2 *radj = nullptr;        // mate adjacency ranges (atomic-maximum claims), grown on demand
     size_t cap_radj = 0;
+    int32_t *prow = nullptr;     // rows recorded by the claims (alternate=fast), grown on demand
+    size_t cap_prow = 0;
     int32_t *cwork = nullptr;
     uint32_t *ctrl = nullptr;
     uint32_t *bar = nullptr;     // grid barrier arrival flags

@@ -48,9 +48,11 @@ enum Flags : uint32_t {
     F_ENDPOINT = 128u,  // WR: one augmenting-path end per root (the first reached), the others released
     F_BAR_COUNTER = 256u, // grid barrier: the last arrival of a counter releases (else block 0 polls flags)
     F_MAXCLAIM = 512u,    // claim a row with one atomic maximum of its stamp (no probe); needs radj
-    F_DEFER = 1024u       // grid levels: frontier slots reserved by the counter barrier's own addition,
+    F_DEFER = 1024u,      // grid levels: frontier slots reserved by the counter barrier's own addition,
                           // entries written after arriving (agent-scope words, -1 once consumed);
                           // needs F_BAR_COUNTER and qcap
+    F_FASTALT = 2048u     // claims record the row behind the claiming column; Alternate follows it
+                          // (two independent loads per step); needs prow
 };
 
 // Device view of one graph plus its working state.
@@ -66,6 +68,8 @@ struct DevGraph {
     int32_t *ends;           // [nr]   unmatched rows reached this phase
     int32_t *clevel;         // [nc]   column levels (F_LEVELS) or null
     uint64_t qcap = 0;       // entries in each of fq0 and fq1 (fq1 = fq0 + qcap; F_DEFER)
+    int32_t *prow = nullptr; // [nr]   F_FASTALT: for a row claimed this phase, the mate of the column it
+                             //        was claimed from (-1 for a root), or null
     int2 *radj = nullptr;    // [nr]   adjacency range {colptr[m], colptr[m+1]} of the row's mate m
                              //        (F_MAXCLAIM; meaningful while the row is matched), or null
     uint32_t *ptrace = nullptr;  // [2 * kPhaseTrace] per phase: BFS levels, unmatched rows reached

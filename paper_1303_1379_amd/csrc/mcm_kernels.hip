@@ -343,7 +343,7 @@ DEV uint32_t block_flush(Stage &st, const QSink &k, int32_t *ge, uint32_t *gecnt
 // claimed as an augmenting-path end (rmatch = -2) and marks its root done.
 template <int S>
 DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, int level, uint32_t flags,
-                    bool &newcol, int4 &ne, bool &newend, bool &tried)
+                    bool &newcol, int4 &ne, bool &newend, bool &tried, int colmate)
 {
     if (flags & F_MAXCLAIM) {
         // Low-degree rows: one atomic maximum of the phase stamp claims the
@@ -360,6 +360,7 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
         const int mate = (int)(uint32_t)old;
         int32_t *lo = reinterpret_cast<int32_t *>(g.rw) + 2 * (size_t)r;
         st_i<S>(&g.pred[r], col);
+        if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
         if (mate >= 0) {
             st_i<S>(lo, mate);
             ne = make_int4(mate, root, adj.x, adj.y);
@@ -388,6 +389,7 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
         const int b = g.colptr[mate], e = g.colptr[mate + 1];
         if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | (uint32_t)mate)) {
             st_i<S>(&g.pred[r], col);
+            if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
             ne = make_int4(mate, root, b, e);
             newcol = true;
             if (flags & F_LEVELS) g.clevel[mate] = level + 1;
@@ -395,6 +397,7 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
     } else if (mate == -1) {
         if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | 0xFFFFFFFEull)) {
             st_i<S>(&g.pred[r], col);
+            if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
             if ((flags & F_WR) && (flags & F_ENDPOINT)) {
                 // the root's path ends at the first unmatched row it reached;
                 // a later one stays marked and FixMatching frees it
@@ -500,13 +503,15 @@ DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, const QSin
     }
 }
 
-template <bool WAVE, int S>
+// SINGLE: a launch for one graph (mcm_match); the others (batches, the
+// server's multi-graph launch) compile the recorded-row Alternate out.
+template <bool WAVE, int S, bool SINGLE = true>
 DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
                           int level, const RunOpt &o, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc,
                           uint32_t local = 0)
 {
     const int lane = __lane_id();
-    const uint32_t flags = o.flags;
+    const uint32_t flags = SINGLE ? o.flags : (o.flags & ~(uint32_t)F_FASTALT);
     const uint64_t t0 = (flags & F_STATS) ? wall_clock64() : 0;
     bool any_end = false;
     const uint32_t B = batch_size(n, nwaves, o.batch_min);
@@ -528,8 +533,10 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
     auto expand = [&](const int4 e, const bool have) {
         int deg = 0;
         uint32_t rdone = 0;
+        int cmate = -1;  // F_FASTALT: the entry column's mate (cmatch does not change during the BFS)
         if (have) {
             deg = e.w - e.z;
+            if (flags & F_FASTALT) cmate = g.cmatch[e.x];
             if (late) rdone = ld_u<S>(&g.cdone[e.y]);
             else if ((flags & F_WR) && deg > 0 && ld_u<S>(&g.cdone[e.y]) == ph) deg = 0;
         }
@@ -555,6 +562,9 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
                 const int oroot = __shfl(e.y, own, 64);
                 const int obeg = __shfl(e.z, own, 64);
                 const int oexcl = __shfl(excl, own, 64);
+                // (every lane takes part in the shuffles: a lane may read an
+                // owner that has no edge of its own in this round)
+                const int omate = (flags & F_FASTALT) ? __shfl(cmate, own, 64) : -1;
                 bool newcol = false, newend = false, tried = false;
                 int4 ne = make_int4(0, 0, 0, 0);
                 int r = 0;
@@ -562,7 +572,7 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
                     r = g.rowind[obeg + (k - oexcl)];
                     const uint32_t odone = late ? (uint32_t)__shfl((int)rdone, own, 64) : 0u;
                     if (!late || odone != ph)
-                        visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend, tried);
+                        visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend, tried, omate);
                 }
                 push_entry(newcol, ne, o.split, st, io.next);
                 push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
@@ -581,7 +591,7 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
                 int r = 0;
                 if (t < deg) {
                     r = g.rowind[e.z + t];
-                    visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend, tried);
+                    visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend, tried, cmate);
                 }
                 push_entry(newcol, ne, o.split, st, io.next);
                 push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
@@ -684,6 +694,33 @@ DEV void alternate(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nth
 {
     uint64_t steps = 0;
     int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);  // low word of rw[r] is rlo[2r]
+    if (flags & F_FASTALT) {
+        // The claim recorded, next to pred[r], the row prow[r] that held
+        // pred[r] during the BFS, so a step loads the two together instead
+        // of cmatch[pred[r]] after pred[r].  Without reading cmatch a walk
+        // cannot see another walk's flips: where several ends of one tree
+        // share the way to the root, each walk flips the shared part with
+        // the same values; at the column where they join, the last flip
+        // wins and FixMatching unmatches the other walk's row, as it does
+        // for a walk that stops there.
+        for (uint32_t i = tid; i < nends; i += nthreads) {
+            int r = g.ends[i];
+            uint32_t guard = 0;
+            for (;;) {
+                const int c = ld_i<S>(&g.pred[r]);
+                const int r2 = ld_i<S>(&g.prow[r]);
+                st_i<S>(&g.cmatch[c], r);
+                st_i<S>(&rlo[2 * (size_t)r], c);
+                if (flags & F_MAXCLAIM) g.radj[r] = make_int2(g.colptr[c], g.colptr[c + 1]);
+                ++steps;
+                if (r2 == -1) break;  // c was a root
+                r = r2;
+                if (++guard > (uint32_t)g.nc + 1u) { set_status(ctrl, kEInternal); break; }
+            }
+        }
+        if (flags & F_STATS) acc.add(S_ALT, steps);
+        return;
+    }
     for (uint32_t i = tid; i < nends; i += nthreads) {
         int r = g.ends[i];
         int c = ld_i<S>(&g.pred[r]);
@@ -991,7 +1028,7 @@ DEV uint32_t level_blocks(uint32_t n, uint32_t per, uint32_t nblocks)
 // progress well within their wait limit.
 constexpr uint32_t kSmallRunLevels = 4096;
 
-template <bool WAVE>
+template <bool WAVE, bool SINGLE = true>
 DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t ph, int L, uint32_t n0,
                          Stage &st, uint32_t *s_tmp, uint32_t *s_loc, Acc &acc, uint32_t *total_levels)
 {
@@ -1016,7 +1053,7 @@ DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uin
         int4 *cur = (L & 1) ? g.fq1 : g.fq0;
         const LevelIO io{QSink{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], nullptr, (flags & F_DEFER) != 0},
                          &s_loc[4], &s_loc[3], ctrl, false};
-        expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
+        expand_level<WAVE, kGroup, SINGLE>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
         ++levels;
         if ((flags & F_APSB) && *(volatile uint32_t *)&s_loc[3]) { stop = 1; break; }
         ++L;
@@ -1036,10 +1073,11 @@ DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uin
 }
 
 // The phase loop of Algorithm 1 over the whole grid (cooperative launch).
-// LOCAL: local levels (option local_levels) in this launch.  Off in the
-// multi-graph launch, where they lengthened the serving latency (p50 45 ->
-// 50 ms at 2000 requests/s) and cost registers.
-template <bool WAVE, bool LOCAL = true>
+// SINGLE: the launch for one graph (mcm_match), with local levels (option
+// local_levels) and the recorded-row Alternate.  The multi-graph launch
+// compiles both out: local levels lengthened the serving latency there
+// (p50 45 -> 50 ms at 2000 requests/s), and both cost registers.
+template <bool WAVE, bool SINGLE = true>
 DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt &o, uint64_t *stats, Acc &acc, Stage &st,
                   uint32_t *s_tmp, uint32_t *s_loc, int *s_ok, uint32_t *ph_out, uint32_t *lv_out, Grp gr,
                   uint32_t &epoch)
@@ -1100,7 +1138,8 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
                 Pub p = none;
                 if (gr.b == 0) {
                     const uint64_t t0 = timing ? wall_clock64() : 0;
-                    const LvState r = small_levels<WAVE>(g, ctrl, o, ph, L, s.n, st, s_tmp, s_loc, acc, &total_levels);
+                    const LvState r =
+                        small_levels<WAVE, SINGLE>(g, ctrl, o, ph, L, s.n, st, s_tmp, s_loc, acc, &total_levels);
                     if (timing) acc.tick(S_T_SMALL, wall_clock64() - t0);
                     p = Pub{r.L, r.n, r.stop, nullptr, nullptr, false};
                 }
@@ -1119,8 +1158,9 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             if (gr.b < active) {
                 int4 *cur = (L & 1) ? g.fq1 : g.fq0;
                 const LevelIO io{next, line(ctrl, L_NENDS), fd(L % 3), ctrl, defer};
-                share = expand_level<WAVE, kAgent>(g, cur, s.n, wave, active * (blockDim.x >> 6), ph, L, o, io, st,
-                                                   s_tmp, acc, (!LOCAL || (flags & F_LEVELS)) ? 0u : o.local_levels);
+                share = expand_level<WAVE, kAgent, SINGLE>(g, cur, s.n, wave, active * (blockDim.x >> 6), ph, L, o,
+                                                           io, st, s_tmp, acc,
+                                                           (!SINGLE || (flags & F_LEVELS)) ? 0u : o.local_levels);
                 if (!(flags & F_APSB)) share &= 0x7fffffffu;
             }
             ++total_levels;
@@ -1139,7 +1179,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         }
         if (ne == 0 || (flags & F_NOAUG)) break;
         const uint64_t ta = timing ? wall_clock64() : 0;
-        alternate<kAgent>(g, ne, tid, nthreads, flags, ctrl, acc);
+        alternate<kAgent>(g, ne, tid, nthreads, SINGLE ? flags : (flags & ~(uint32_t)F_FASTALT), ctrl, acc);
         if (!sync_all(none)) return false;
         fix_matching(g, tid, nthreads, flags, acc);
         if ((flags & F_DEFER) && left.stop) {
@@ -1183,14 +1223,14 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, Acc &acc,
             int4 *cur = (L & 1) ? g.fq1 : g.fq0;
             const LevelIO io{QSink{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], nullptr, false}, &s_loc[4],
                              &s_loc[3], ctrl, false};
-            expand_level<WAVE, kGroup>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
+            expand_level<WAVE, kGroup, false>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
             ++total_levels;
             if ((flags & F_APSB) && *(volatile uint32_t *)&s_loc[3]) break;
             ++L;
         }
         const uint32_t ne = *(volatile uint32_t *)&s_loc[4];
         if (ne == 0 || (flags & F_NOAUG)) break;
-        alternate<kGroup>(g, ne, threadIdx.x, blockDim.x, flags, ctrl, acc);
+        alternate<kGroup>(g, ne, threadIdx.x, blockDim.x, flags & ~(uint32_t)F_FASTALT, ctrl, acc);
         __syncthreads();
         fix_matching(g, threadIdx.x, blockDim.x, flags, acc);
     }

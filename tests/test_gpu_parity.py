@@ -30,7 +30,8 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels=6)
+                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels=6,
+                alternate="auto")
 
 
 @pytest.fixture(autouse=True)
@@ -262,23 +263,48 @@ def test_local_levels(local, combo, name):
 
 @pytest.mark.parametrize("name,low", [("grid256p", True), ("uniform2000", True), ("rmat15", False)])
 def test_auto_claim_and_flush(name, low):
-    """claim, flush and wr_check on auto pick the atomic maximum, deferred
-    levels and the root test beside the edge visit for graphs with at most 8
-    edges per row on average, the probe, the queue atomic and the root test
-    before the scan otherwise; deferred levels need the device loop and the
-    counter barrier."""
+    """claim, flush, wr_check and alternate on auto pick the atomic maximum,
+    deferred levels, the root test beside the edge visit and the recorded-row
+    Alternate for graphs with at most 8 edges per row on average, the probe,
+    the queue atomic, the root test before the scan and the classic Alternate
+    otherwise; deferred levels need the device loop and the counter
+    barrier."""
     g = gg.workload(name)
     ref = _oracle_card(g)
     _set(wg_threshold=0)
     assert _gpu(g, certify=False)[0] == ref
     s = mcm.last_stats()
-    assert (s["claim"], s["flush"], s["wr_check"]) == ((1, 1, 1) if low else (0, 0, 0))
+    assert (s["claim"], s["flush"], s["wr_check"], s["alternate"]) == ((1, 1, 1, 1) if low else (0, 0, 0, 0))
     _set(loop="host")
     assert _gpu(g, certify=False)[0] == ref
     assert mcm.last_stats()["flush"] == 0
     _set(loop="device", barrier="flags")
     assert _gpu(g, certify=False)[0] == ref
     assert mcm.last_stats()["flush"] == 0
+
+
+# Alternate following the rows recorded at the claims (fast) or reading
+# cmatch at each step (classic): several ends per root (APFB, shared ways to
+# the root, junction conflicts), one end per root (APsB), both mappings (the
+# wave mapping hands each edge its entry's recorded row across lanes, also in
+# rounds where the owner lane has no edge of its own), both level loops, and
+# local levels on and off.  grid128 and rmat13 are where a lane-shuffle
+# mistake once recorded wrong rows.
+ALT_COMBOS = [dict(driver="apfb", mapping="wave", loop="device", endpoints="all"),
+              dict(driver="apfb", mapping="thread", loop="device", endpoints="all", local_levels=0),
+              dict(driver="apsb", mapping="wave", loop="device", endpoints="one"),
+              dict(driver="apfb", mapping="wave", loop="host", endpoints="all"),
+              dict(driver="apsb", mapping="thread", loop="host", endpoints="all")]
+
+
+@pytest.mark.parametrize("alt", ["fast", "classic"])
+@pytest.mark.parametrize("combo", ALT_COMBOS, ids=lambda c: "-".join(str(v) for v in c.values()))
+@pytest.mark.parametrize("name", ["grid128", "rmat13", "uniform2000", "grid256p"])
+def test_alternate_forms(alt, combo, name):
+    g = gg.workload(name)
+    _set(wg_threshold=0, alternate=alt, **combo)
+    assert _gpu(g)[0] == _oracle_card(g), (alt, combo)
+    assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (alt, combo)
 
 
 def test_deferred_levels_repeated():
