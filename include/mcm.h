@@ -351,9 +351,10 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              reads cmatch after pred and
  *                                              stops where another walk
  *                                              passed (classic, as printed);
- *                                              auto = fast for graphs with
- *                                              at most 8 edges per row on
- *                                              average, classic otherwise
+ *                                              auto = fast with GPUBFS-WR
+ *                                              on graphs with at most 8
+ *                                              edges per row on average,
+ *                                              classic otherwise
  *   "local_levels" "6" (default) | "0".."16"   levels of mcm_match's
  *                                              persistent loop (not the
  *                                              multi-graph launch of

@@ -735,8 +735,9 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     g.qcap = w.cap_q;
     // Alternate along recorded rows where walks are long (low-degree graphs:
     // grid2048 430 -> 413 ms); on skewed graphs the extra load per entry
-    // and store per claim cost more than their short walks save.
-    if (o.alternate == 1 || (o.alternate == 2 && low_degree)) {
+    // and store per claim cost more than their short walks save, and without
+    // WR (many ends per tree) walks would repeat their shared ways.
+    if (o.alternate == 1 || (o.alternate == 2 && low_degree && o.wr)) {
         if ((rc = ensure_prow(w, (size_t)nrows))) return rc;
         g.prow = w.prow;
         flags |= F_FASTALT;
