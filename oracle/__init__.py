@@ -9,7 +9,10 @@ numpy arrays.
 What it computes (paper, section 2 and section 3):
   * cheap_init      -- the greedy initial matching every run starts from
                        (section 4, experimental setup);
+  * check_csc       -- the input is well formed (step 0 of every run);
   * hopcroft_karp   -- maximum matching from a given matching (section 2);
+    hopcroft_karp_ex and hopcroft_karp_sample run it phase-bounded and
+    count the adjacency entries read (the CPU baseline);
   * konig_cover     -- a vertex cover of size |M| from the final alternating
                        BFS (Berge / Konig: certifies maximality);
   * verify_cover    -- an independent weak-duality certificate check;
@@ -125,6 +128,26 @@ def hopcroft_karp(g, cmatch=None, rmatch=None, timed: bool = False):
         raise MemoryError("orc_hopcroft_karp failed")
     out = (int(card), cm[:nc].copy(), rm[:nr].copy(), int(ph.value))
     return out + (dt,) if timed else out
+
+
+def hopcroft_karp_ex(g, cmatch, rmatch, max_phases: int | None = None):
+    """Hopcroft-Karp from (cmatch, rmatch), at most `max_phases` augmenting
+    phases (None: until maximum).  Returns (card, cmatch, rmatch, phases,
+    edges_scanned), edges_scanned counting the adjacency entries read by the
+    BFS and DFS steps of every phase run, including the last BFS."""
+    nc, nr, cp, ri = _g(g)
+    cm = np.full(max(nc, 1), -1, np.int32)
+    rm = np.full(max(nr, 1), -1, np.int32)
+    cm[:nc] = cmatch
+    rm[:nr] = rmatch
+    ph = ctypes.c_int64(0)
+    ed = ctypes.c_int64(0)
+    lim = (1 << 63) - 1 if max_phases is None else int(max_phases)
+    card = _load().orc_hopcroft_karp_ex(nc, nr, cp.ctypes.data, ri.ctypes.data, cm.ctypes.data, rm.ctypes.data, lim,
+                                        ctypes.addressof(ph), ctypes.addressof(ed))
+    if card < 0:
+        raise MemoryError("orc_hopcroft_karp_ex failed")
+    return int(card), cm[:nc].copy(), rm[:nr].copy(), int(ph.value), int(ed.value)
 
 
 def hopcroft_karp_sample(g, cmatch, rmatch, budget_s: float = 15.0):

@@ -308,3 +308,127 @@ def test_fig1_worked_example():
     assert card == d["expect_card"] and phases == 1
     assert O.brute_force(g) == d["expect_card"]
     assert _certify(g, cm2, rm2) == d["expect_card"]
+
+
+# ------------------------------------------------------------ input check (O0)
+class _Raw:
+    """A CSC pattern as given, without the generators' normalisation."""
+
+    def __init__(self, nc, nr, colptr, rowind):
+        self.nc, self.nr = nc, nr
+        self.colptr = np.asarray(colptr, np.int32)
+        self.rowind = np.asarray(rowind, np.int32)
+
+
+def _scipy_accepts(g):
+    """Independent decision: scipy's full structural check of a CSC matrix
+    (index pointer starts at 0 and never decreases, indices in range)."""
+    import scipy.sparse as sp
+    try:
+        a = sp.csc_matrix((np.ones(len(g.rowind)), g.rowind, g.colptr), shape=(g.nr, g.nc))
+        a.check_format(full_check=True)
+        return True
+    except ValueError:
+        return False
+
+
+@pytest.mark.parametrize("nc,nr,colptr,rowind,ok", [
+    (3, 3, [0, 1, 2, 3], [0, 1, 2], True),
+    (0, 0, [0], [], True),
+    (0, 4, [0], [], True),
+    (2, 2, [0, 2, 2], [1, 1], True),             # duplicates and an empty column are well formed
+    (2, 3, [0, 2, 3], [2, 0, 1], True),          # rows of a column in any order
+    (3, 3, [1, 1, 2, 3], [0, 1, 2, 0], False),   # colptr[0] != 0
+    (3, 3, [0, 2, 1, 3], [0, 1, 2], False),      # colptr decreases
+    (3, 3, [0, 1, 2, 3], [0, 1, 3], False),      # row index = nr
+    (3, 3, [0, 1, 2, 3], [0, -1, 2], False),     # negative row index
+    (1, 0, [0, 1], [0], False),                  # an edge in a graph without rows
+])
+def test_check_csc_hand_cases(nc, nr, colptr, rowind, ok):
+    g = _Raw(nc, nr, colptr, rowind)
+    assert O.check_csc(g) == ok
+    assert _scipy_accepts(g) == ok
+
+
+def test_check_csc_rejects_negative_sizes():
+    assert not O.check_csc(_Raw(-1, 3, [0], []))
+    assert not O.check_csc(_Raw(2, -1, [0, 0, 0], []))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_check_csc_agrees_with_scipy_on_planted_faults(seed):
+    """A well-formed random pattern with at most one planted fault (colptr
+    start, a decrease inside colptr, a row index out of range on either
+    side): the oracle's verdict equals scipy's."""
+    rng = np.random.default_rng(7000 + seed)
+    g0 = gg.uniform(int(rng.integers(1, 40)), int(rng.integers(1, 40)), 3, seed)
+    cp, ri = g0.colptr.copy(), g0.rowind.copy()
+    fault = seed % 5
+    if fault == 1:
+        cp[0] = 1
+    elif fault == 2 and g0.nc >= 2:
+        c = int(rng.integers(1, g0.nc))
+        cp[c] = cp[c + 1] + 1                    # cp[c] > cp[c + 1]: decreasing
+    elif fault == 3 and len(ri):
+        ri[int(rng.integers(0, len(ri)))] = g0.nr
+    elif fault == 4 and len(ri):
+        ri[int(rng.integers(0, len(ri)))] = -1 - int(rng.integers(0, 5))
+    g = _Raw(g0.nc, g0.nr, cp, ri)
+    assert O.check_csc(g) == _scipy_accepts(g)
+
+
+def test_generated_workloads_are_well_formed():
+    for name in ("uniform2000", "grid64", "rmat12"):
+        g = gg.workload(name)
+        assert O.check_csc(g) and _scipy_accepts(g)
+
+
+# ------------------------------------------------------------ bounded Hopcroft-Karp (the CPU-baseline sample)
+def _two_phase_graph():
+    """Hand-worked instance.  Columns c0, c1, c2; rows r0, r1, r2; edges
+    c0-r0, c1-r1, c2-r1, c2-r2 (rows of c2 stored r1 then r2); initial
+    matching {c2-r1}.  Phase 1: the BFS layers c0, c1 (distance 0) and c2
+    (distance 1, the mate of r1); r0 is free next to c0, so the shortest
+    augmenting path has one column and only c0-r0 is augmented; the path
+    c1-r1-c2-r2 (two columns) is left for phase 2.  Edges read, phase 1:
+    BFS c0 (1) + c1 (1), c2 is not scanned (its distance reaches the limit);
+    DFS from c0 reads r0 (1), from c1 reads r1 (1) and descends to c2, which
+    reads r1 and r2 (2) before it is exhausted: 6 in all.  Phase 2: BFS
+    c1 (1) + c2 (2), DFS c1 reads r1 (1), c2 reads r1, r2 (2) and augments:
+    6 again.  A third BFS starts from no unmatched column: 0."""
+    g = gg.from_edges(3, 3, [(0, 0), (1, 1), (2, 1), (2, 2)])
+    cm = np.array([-1, -1, 1], np.int32)
+    rm = np.array([-1, 2, -1], np.int32)
+    return g, cm, rm
+
+
+def test_bounded_hk_one_phase_is_valid_and_not_maximum():
+    g, cm0, rm0 = _two_phase_graph()
+    assert O.brute_force(g) == 3
+    card, cm, rm, phases, edges = O.hopcroft_karp_ex(g, cm0, rm0, max_phases=1)
+    assert (card, phases, edges) == (2, 1, 6)
+    assert O.check_matching(g, cm, rm) == 2
+    assert cm.tolist() == [0, -1, 1] and rm.tolist() == [0, 2, -1]
+    assert O.konig_cover(g, cm, rm)[0] == -3          # not maximum: an augmenting path is left
+    card, cm, rm, phases, edges = O.hopcroft_karp_ex(g, cm0, rm0)
+    assert (card, phases, edges) == (3, 2, 12)
+    assert _certify(g, cm, rm) == 3
+
+
+def test_bounded_hk_sample_adds_up_to_the_complete_run():
+    g, cm0, rm0 = _two_phase_graph()
+    s = O.hopcroft_karp_sample(g, cm0, rm0, budget_s=60.0)
+    assert s == {**s, "phases": 2, "edges": 12, "card": 3, "done": True}
+    # on a larger input: phase by phase, the same phases, edges and result as one complete run
+    g = gg.workload("grid64")
+    cm0, rm0 = O.cheap_init(g)
+    card, _, _, phases, edges = O.hopcroft_karp_ex(g, cm0, rm0)
+    s = O.hopcroft_karp_sample(g, cm0, rm0, budget_s=60.0)
+    assert s["done"] and (s["card"], s["phases"], s["edges"]) == (card, phases, edges)
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import maximum_bipartite_matching
+    a = sp.csc_matrix((np.ones(g.nnz), g.rowind, g.colptr), shape=(g.nr, g.nc))
+    assert card == int((maximum_bipartite_matching(a.tocsr(), perm_type="column") >= 0).sum())
+    # a budget of zero runs no phase
+    s0 = O.hopcroft_karp_sample(g, cm0, rm0, budget_s=0.0)
+    assert s0["phases"] == 0 and s0["edges"] == 0 and not s0["done"]

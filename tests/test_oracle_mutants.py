@@ -37,7 +37,29 @@ MUTANTS = {
                           "if (!col_in_cover[c] && !row_in_cover[rowind[j]] && 0) return 2;"),
     # brute force lets a column take a used row
     "brute_reuses_row": ("if (mask & bit) continue;", "(void)0;"),
+    # input check: colptr need not start at 0
+    "csc_no_start_check": ("if (colptr[0] != 0) return -1;", "(void)0;"),
+    # input check: a decreasing colptr passes
+    "csc_accepts_decrease": ("if (colptr[c + 1] < colptr[c]) return -1;", "(void)0;"),
+    # input check: row index nr passes (off by one)
+    "csc_row_bound_off_by_one": ("rowind[j] >= nr", "rowind[j] > nr"),
+    # bounded run: the DFS reads are not counted
+    "hk_edges_skip_dfs": ("                ++nedges;\n", "\n"),
+    # bounded run: the phase bound is ignored
+    "hk_phase_bound_ignored": ("if (nph >= max_phases) break;", "(void)0;"),
 }
+
+# (nc, nr, colptr, rowind, well formed)
+CSC_CASES = [(3, 3, [0, 1, 2, 3], [0, 1, 2], True), (2, 2, [0, 2, 2], [1, 1], True),
+             (3, 3, [1, 1, 2, 3], [0, 1, 2, 0], False), (3, 3, [0, 2, 1, 3], [0, 1, 2], False),
+             (3, 3, [0, 1, 2, 3], [0, 1, 3], False), (3, 3, [0, 1, 2, 3], [0, -1, 2], False)]
+
+
+class _Raw:
+    def __init__(self, nc, nr, colptr, rowind):
+        self.nc, self.nr = nc, nr
+        self.colptr = np.asarray(colptr, np.int32)
+        self.rowind = np.asarray(rowind, np.int32)
 
 
 def _build_mutant(name):
@@ -88,6 +110,18 @@ def _pins_hold(so):
         for m, n in [(3, 5), (6, 6)]:
             if O.hopcroft_karp(gg.complete(m, n))[0] != min(m, n):
                 return False
+        for nc, nr, cp, ri, ok in CSC_CASES:
+            if O.check_csc(_Raw(nc, nr, cp, ri)) != ok:
+                return False
+        # the hand-worked two-phase instance of test_oracle (counts derived there)
+        g = gg.from_edges(3, 3, [(0, 0), (1, 1), (2, 1), (2, 2)])
+        cm0, rm0 = np.array([-1, -1, 1], np.int32), np.array([-1, 2, -1], np.int32)
+        card, _, _, ph, ed = O.hopcroft_karp_ex(g, cm0, rm0, max_phases=1)
+        if (card, ph, ed) != (2, 1, 6):
+            return False
+        card, _, _, ph, ed = O.hopcroft_karp_ex(g, cm0, rm0)
+        if (card, ph, ed) != (3, 2, 12):
+            return False
         return True
     finally:
         O._LIB = real
