@@ -11,8 +11,12 @@
  *     column (Algorithm 2 "GPUBFS"; Algorithm 4 "GPUBFS-WR" adds the root
  *     and stops expanding a tree once its root has found an unmatched row);
  *   - Alternate (Algorithm 3): from every unmatched row found, flip the
- *     matched/unmatched edges back along the predecessor chain, stopping
- *     where another flip already passed;
+ *     matched/unmatched edges back along the predecessor chain to the
+ *     root.  Walks of one tree that share a way to the root either stop
+ *     where another walk already flipped (the check of Algorithm 3, option
+ *     "alternate" "classic") or flip the shared part alike (option "fast",
+ *     the default on low-degree graphs), and then the last flip of the
+ *     column where they join wins;
  *   - FixMatching: unmatch every row whose column no longer points back.
  * APFB (the default driver) keeps expanding BFS levels until the frontier
  * is empty; APsB stops at the first level that finds an unmatched row
@@ -36,6 +40,11 @@
  *     exception crosses this interface.
  *   - Concurrency: entry points may be called from several host threads;
  *     calls that share the library workspace are serialised internally.
+ *     The library keeps at most one cooperative (whole-device) launch in
+ *     flight in the process: mcm_match, mcm_konig_cover and mcm_bfs_levels
+ *     on graphs above the one-workgroup size, the multi-graph launches of
+ *     mcm_match_batched and of a request server take turns; a server's
+ *     large requests wait while another caller's launch runs.
  */
 #ifndef MCM_H
 #define MCM_H
@@ -264,6 +273,35 @@ int64_t mcm_bfs_levels(int32_t ncols, int32_t nrows, const int32_t *colptr, cons
                        int32_t *col_level, int32_t *row_pred, void *stream);
 
 /*
+ * mcm_bfs_forest -- one complete BFS phase of the form mcm_match would run
+ * (GPUBFS-WR of Algorithm 4 by default, GPUBFS of Algorithm 2 with option
+ * "bfs" "plain"), without augmentation and strictly level-synchronous (one
+ * BFS level per grid level), from every unmatched column of the given
+ * matching.  It exposes the forest the phase grows, for inspection and for
+ * checking the GPUBFS-WR invariants: with the early exit, a tree whose root
+ * has found an unmatched row stops growing one level later, the columns
+ * reached are a subset of those GPUBFS reaches, and every column's root is
+ * the root of the column that reached its matched row.  The options
+ * "endpoints" ("one": one end per root), "claim" ("max"), "flush"
+ * ("defer") and "wr_check" select the same forms as for mcm_match ("auto"
+ * means the plain default here).
+ *
+ *   col_level  [ncols] device output: the level at which each column
+ *              entered the BFS (0 for unmatched columns), -1 if not reached
+ *   col_root   [ncols] device output: the unmatched column at the root of
+ *              its tree (itself for an unmatched column), -1 if not reached
+ *   row_pred   [nrows] device output: the column that claimed each row,
+ *              -1 if not reached
+ *   ends       [nrows] device output: the unmatched rows reached that
+ *              Alternate would start from, in the first entries
+ * Returns the number of ends, or a negative mcm_status.
+ */
+int64_t mcm_bfs_forest(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                       const int32_t *cmatch, const int32_t *rmatch,
+                       int32_t *col_level, int32_t *col_root, int32_t *row_pred, int32_t *ends,
+                       void *stream);
+
+/*
  * mcm_cheap_init_host -- the greedy initial matching that precedes every
  * run in the paper's experiments (section 4): columns in index order, each
  * takes the first row of its stored adjacency that is still unmatched.
@@ -418,7 +456,7 @@ typedef struct {
     double  t_barrier_ms;    /*   waiting in grid barriers, */
     double  t_small_ms;      /*   running single-workgroup levels, */
     double  t_augment_ms;    /*   in Alternate and FixMatching */
-    int64_t init_card;       /* |M| of the initial matching */
+    int64_t init_card;       /* |M| of the initial matching (mcm_match; -1 after a batched call) */
     int64_t card;            /* |M| returned */
     double  kernel_ms;       /* device time of the matching, HIP events */
     int32_t loop;            /* 0 = device-side level loop, 1 = host-side */
@@ -439,6 +477,16 @@ const char *mcm_strerror(int64_t status);
 
 /* Library version string. */
 const char *mcm_version(void);
+
+/*
+ * mcm_shutdown -- releases everything the library holds on every device:
+ * workspaces, pinned host buffers, events, and the batch plans and request
+ * servers the caller has not destroyed (a later destroy call on such a
+ * handle does nothing).  Call it before the process tears down the HIP
+ * runtime (the Python binding registers it with atexit).  The library may
+ * be used again afterwards; it allocates anew.  Returns MCM_OK.
+ */
+int mcm_shutdown(void);
 
 #ifdef __cplusplus
 }

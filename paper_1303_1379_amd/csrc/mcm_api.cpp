@@ -12,13 +12,37 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <vector>
 
 using namespace mcm;
 
 namespace mcm {
+
+CoopGate &coop_gate()
+{
+    static CoopGate g;
+    return g;
+}
+
 namespace host {
+
+// ------------------------------------------------------------------ live handles
+std::mutex g_handles_mu;
+std::map<void *, void (*)(void *)> g_handles;
+
+void register_handle(void *h, void (*destroy)(void *))
+{
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    g_handles[h] = destroy;
+}
+
+bool unregister_handle(void *h)
+{
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    return g_handles.erase(h) == 1;
+}
 
 // ------------------------------------------------------------------ errors
 thread_local std::string t_err;
@@ -60,6 +84,23 @@ std::vector<uint32_t> g_phases;  // per-phase (levels, ends) of the last stats r
 void free_dev(void *p)
 {
     if (p) (void)hipFree(p);
+}
+
+// Releases everything a device workspace holds (mcm_shutdown).
+static void release_workspace(Workspace &w)
+{
+    if (w.device < 0) return;
+    (void)hipSetDevice(w.device);
+    (void)hipDeviceSynchronize();
+    for (void *p : {(void *)w.rw, (void *)w.pred, (void *)w.cdone, (void *)w.fq, (void *)w.ends, (void *)w.radj,
+                    (void *)w.prow, (void *)w.cwork, (void *)w.ctrl, (void *)w.bar, (void *)w.desc, (void *)w.mctrl,
+                    (void *)w.mbar, (void *)w.order, (void *)w.card, (void *)w.ptrace})
+        free_dev(p);
+    for (void *p : {(void *)w.h_ptrace, (void *)w.h_ctrl, (void *)w.h_desc, (void *)w.h_order, (void *)w.h_card})
+        if (p) (void)hipHostFree(p);
+    if (w.ev0) (void)hipEventDestroy(w.ev0);
+    if (w.ev1) (void)hipEventDestroy(w.ev1);
+    w = Workspace();
 }
 
 int64_t ensure_base(Workspace &w, int dev)
@@ -669,13 +710,24 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows, std::max(qcap, (size_t)ncols)))) return rc;
 
     if (o.validate) {
+        // the structure first; the initial matching (whose on-edge check
+        // scans column ranges of rowind) only on a sound structure
+        auto status = [&]() -> int64_t {
+            HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            return (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
+        };
         HIPCHK(launch_zero_ctrl(w.ctrl, st));
-        HIPCHK(launch_validate(ncols, nrows, colptr, rowind, init_cmatch, init_rmatch, w.ctrl, st));
-        HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
+        HIPCHK(launch_validate_csc(ncols, nrows, colptr, rowind, w.ctrl, st));
+        int64_t s = status();
         if (s == MCM_EINVAL) return fail(MCM_EINVAL, "malformed CSC input");
-        if (s == MCM_EBADINIT) return fail(MCM_EBADINIT, "initial matching is inconsistent or not on edges");
+        if (s < 0) return s;
+        if (init_cmatch) {
+            HIPCHK(launch_validate_init(ncols, nrows, colptr, rowind, init_cmatch, init_rmatch, w.ctrl, st));
+            s = status();
+            if (s == MCM_EBADINIT) return fail(MCM_EBADINIT, "initial matching is inconsistent or not on edges");
+            if (s < 0) return s;
+        }
     }
 
     uint32_t flags = base_flags(o, ncols, 0);
@@ -708,6 +760,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
         loop = 2;
         int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
         int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
+        init_card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_INIT_CARD));
         record_stats(w.h_ctrl, init_card, card, ms, loop, flags, w.info.clock_khz);
         record_phases(nullptr, 0);  // the one-workgroup path keeps no per-phase record
         if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
@@ -742,6 +795,7 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
         g.prow = w.prow;
         flags |= F_FASTALT;
     }
+    CoopHold hold(stream, st);  // at most one cooperative launch in flight in the process
     HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, w.bar, flags, st));
     if ((rc = run_graph(w, o, g, flags, st, &loop))) return rc;
     HIPCHK(launch_finish(g, out_rmatch, w.ctrl, st));
@@ -750,17 +804,24 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     HIPCHK(hipEventElapsedTime(&ms, w.ev0, w.ev1));
     const int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
     const int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
+    init_card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_INIT_CARD));
     record_stats(w.h_ctrl, init_card, card, ms, loop, flags, w.info.clock_khz);
     record_phases((flags & F_STATS) ? w.h_ptrace : nullptr, *ctrl_line(w.h_ctrl, L_PHASE));
     if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
     return card;
 }
 
-// Shared by mcm_konig_cover and mcm_bfs_levels: one complete BFS phase
-// (GPUBFS, no early exit) from the caller's matching, on workspace copies.
+// Shared by mcm_konig_cover, mcm_bfs_levels and mcm_bfs_forest: one
+// complete BFS phase (no augmentation) from the caller's matching, on
+// workspace copies, strictly level-synchronous.  Without `forest` it is
+// GPUBFS with compare-and-swap claims (the schedule-independent level sets);
+// with it, the BFS form the options select for mcm_match: GPUBFS-WR or
+// GPUBFS ("bfs"), one end per root or all ("endpoints" one / other), claims
+// by atomic maximum when "claim" is "max", deferred levels when "flush" is
+// "defer", root test early or late ("wr_check").
 static int64_t one_bfs_phase(Workspace &w, const Options &o, int32_t nc, int32_t nr, const int32_t *colptr,
                              const int32_t *rowind, const int32_t *cm, const int32_t *rm, int32_t *clevel,
-                             hipStream_t st, DevGraph *gout)
+                             int32_t *croot, bool forest, hipStream_t st, DevGraph *gout)
 {
     int64_t rc;
     size_t qcap = 0;
@@ -779,8 +840,22 @@ static int64_t one_bfs_phase(Workspace &w, const Options &o, int32_t nc, int32_t
     g.fq1 = w.fq + w.cap_q;
     g.ends = w.ends;
     g.clevel = clevel;
+    g.croot = croot;
+    g.qcap = w.cap_q;
     uint32_t flags = F_NOAUG | (clevel ? F_LEVELS : 0u);
     if (o.mapping != 0) flags |= F_WAVE;
+    if (forest) {
+        if (o.wr) flags |= F_WR;
+        if (o.wr_check != 0) flags |= F_WR_LATE;
+        if (o.endpoints == 1) flags |= F_ENDPOINT;
+        if (o.bar_counter) flags |= F_BAR_COUNTER;
+        if (o.bar_counter && o.loop != 1 && o.flush == 1) flags |= F_DEFER;
+        if (o.claim == 1) {
+            if ((rc = ensure_radj(w, (size_t)nr))) return rc;
+            g.radj = w.radj;
+            flags |= F_MAXCLAIM;
+        }
+    }
     HIPCHK(launch_setup(g, cm, rm, w.ctrl, w.bar, flags, st));
     int loop = 0;
     Options oo = o;
@@ -813,8 +888,10 @@ int64_t mcm_konig_cover(int32_t ncols, int32_t nrows, const int32_t *colptr, con
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace &w = g_ws[dev];
     if ((rc = ensure_base(w, dev))) return rc;
+    CoopHold hold(stream, st);
     DevGraph g;
-    if ((rc = one_bfs_phase(w, o, ncols, nrows, colptr, rowind, cmatch, rmatch, nullptr, st, &g))) return rc;
+    if ((rc = one_bfs_phase(w, o, ncols, nrows, colptr, rowind, cmatch, rmatch, nullptr, nullptr, false, st, &g)))
+        return rc;
     if (*ctrl_line(w.h_ctrl, L_NENDS) != 0) return fail(MCM_ENOTMAX, "the matching admits an augmenting path");
     HIPCHK(launch_cover(g, 1, col_in_cover, row_in_cover, w.ctrl, st));
     HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
@@ -844,11 +921,71 @@ int64_t mcm_bfs_levels(int32_t ncols, int32_t nrows, const int32_t *colptr, cons
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace &w = g_ws[dev];
     if ((rc = ensure_base(w, dev))) return rc;
+    CoopHold hold(stream, st);
     DevGraph g;
-    if ((rc = one_bfs_phase(w, o, ncols, nrows, colptr, rowind, cmatch, rmatch, col_level, st, &g))) return rc;
+    if ((rc = one_bfs_phase(w, o, ncols, nrows, colptr, rowind, cmatch, rmatch, col_level, nullptr, false, st, &g)))
+        return rc;
     HIPCHK(launch_export_pred(g, 1, row_pred, st));
     HIPCHK(hipStreamSynchronize(st));
     return (int64_t)*ctrl_line(w.h_ctrl, L_NENDS);
+}
+
+int64_t mcm_bfs_forest(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                       const int32_t *cmatch, const int32_t *rmatch, int32_t *col_level, int32_t *col_root,
+                       int32_t *row_pred, int32_t *ends, void *stream)
+{
+    int64_t rc;
+    if ((rc = check_graph_args(ncols, nrows, colptr, rowind))) return rc;
+    if ((ncols > 0 && (!cmatch || !col_level || !col_root)) || (nrows > 0 && (!rmatch || !row_pred || !ends)))
+        return fail(MCM_EINVAL, "NULL matching or output array");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if ((rc = check_null_rowind(ncols, nrows, colptr, rowind, st))) return rc;
+    if (ncols == 0 || nrows == 0) {
+        // no edges: every column is unmatched, its own root at level 0
+        std::vector<int32_t> id((size_t)ncols);
+        std::iota(id.begin(), id.end(), 0);
+        if (nrows > 0) HIPCHK(hipMemsetAsync(row_pred, 0xff, sizeof(int32_t) * nrows, st));
+        if (ncols > 0) {
+            HIPCHK(hipMemsetAsync(col_level, 0, sizeof(int32_t) * ncols, st));
+            HIPCHK(hipMemcpyAsync(col_root, id.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        return 0;
+    }
+    int dev = 0;
+    if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
+    const Options o = opts();
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[dev];
+    if ((rc = ensure_base(w, dev))) return rc;
+    CoopHold hold(stream, st);
+    DevGraph g;
+    if ((rc = one_bfs_phase(w, o, ncols, nrows, colptr, rowind, cmatch, rmatch, col_level, col_root, true, st, &g)))
+        return rc;
+    const uint32_t nends = *ctrl_line(w.h_ctrl, L_NENDS);
+    HIPCHK(launch_export_pred(g, 1, row_pred, st));
+    if (nends) HIPCHK(hipMemcpyAsync(ends, g.ends, sizeof(int32_t) * nends, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return (int64_t)nends;
+}
+
+int mcm_shutdown(void)
+{
+    std::vector<std::pair<void *, void (*)(void *)>> live;
+    {
+        std::lock_guard<std::mutex> lk(g_handles_mu);
+        live.assign(g_handles.begin(), g_handles.end());
+        g_handles.clear();
+    }
+    for (auto &h : live) h.second(h.first);
+    int dev = 0;
+    const bool have_dev = current_device(&dev) == 0;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        for (auto &w : g_ws) release_workspace(w);
+    }
+    if (have_dev) (void)hipSetDevice(dev);
+    return MCM_OK;
 }
 
 }  // extern "C"

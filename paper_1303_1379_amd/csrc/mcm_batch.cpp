@@ -12,6 +12,7 @@
 #include <fstream>
 #include <map>
 #include <numeric>
+#include <optional>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -251,6 +252,9 @@ int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs, const int32_
     }
     RunOpt mro = run_opt(o, flags, std::max<int64_t>(ex.col_ext, 1), w.info);
     mro.split = 0;  // same queue slices as above
+    // the multi-graph launch is cooperative: at most one such launch in flight in the process
+    std::optional<CoopHold> hold;
+    if (nlarge) hold.emplace(stream, st);
     HIPCHK(hipMemcpyAsync(w.desc, w.h_desc, sizeof(BatchDesc) * (ngraphs + nlarge), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(w.order, w.h_order, sizeof(int32_t) * ngraphs, hipMemcpyHostToDevice, st));
     HIPCHK(launch_zero_ctrl(w.ctrl, st));
@@ -482,6 +486,7 @@ int64_t mcm_batch_plan_create(int32_t ngraphs, const mcm_graph *graphs, const in
     p->ro.batch_min = (uint32_t)p->cfg.batch_min;
     p->blocks = batch_blocks(info, p->cfg.wave, p->cfg.block, ngraphs);
     if ((rc = plan_capture(p))) return bail(rc);
+    register_handle(p, [](void *h) { plan_free(static_cast<mcm_batch_plan *>(h)); });
     *plan = p;
     return 0;
 }
@@ -524,7 +529,8 @@ int mcm_batch_plan_info(const mcm_batch_plan *p, char *buf, int32_t len)
 
 int mcm_batch_plan_destroy(mcm_batch_plan *p)
 {
-    plan_free(p);
+    // a plan that mcm_shutdown already released is not freed twice
+    if (p && unregister_handle(p)) plan_free(p);
     return MCM_OK;
 }
 

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/mcm.h"
+#include "mcm_gate.h"
 #include "mcm_internal.h"
 
 namespace mcm {
@@ -17,8 +18,9 @@ namespace mcm {
 hipError_t launch_zero_ctrl(uint32_t *ctrl, hipStream_t st);
 hipError_t launch_setup(const DevGraph &, const int32_t *, const int32_t *, uint32_t *, uint32_t *, uint32_t,
                         hipStream_t);
-hipError_t launch_validate(int32_t, int32_t, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
-                           uint32_t *, hipStream_t);
+hipError_t launch_validate_csc(int32_t, int32_t, const int32_t *, const int32_t *, uint32_t *, hipStream_t);
+hipError_t launch_validate_init(int32_t, int32_t, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
+                                uint32_t *, hipStream_t);
 hipError_t persistent_occupancy(bool, int, int *);
 hipError_t launch_persistent(const DevGraph &, uint32_t *, uint32_t *, const RunOpt &, bool, int, int, hipStream_t);
 hipError_t launch_init_roots(const DevGraph &, uint32_t *, const RunOpt &, hipStream_t);
@@ -40,6 +42,31 @@ hipError_t launch_multi(const BatchDesc *descs, int32_t ngraphs, int group, int 
                         uint32_t *bars, int64_t *card, const RunOpt &o, bool wave, int block, hipStream_t st);
 
 namespace host {
+
+// Holds the cooperative-launch gate for `owner` from construction until
+// destruction; the destructor first waits for `stream`, so that the gate is
+// released only once every launch made under it has completed, on every
+// return path.
+class CoopHold {
+  public:
+    CoopHold(const void *owner, hipStream_t stream) : owner_(owner), st_(stream) { coop_gate().enter(owner_); }
+    ~CoopHold()
+    {
+        (void)hipStreamSynchronize(st_);
+        coop_gate().leave(owner_);
+    }
+    CoopHold(const CoopHold &) = delete;
+    CoopHold &operator=(const CoopHold &) = delete;
+
+  private:
+    const void *owner_;
+    hipStream_t st_;
+};
+
+// Live batch plans and servers, so that mcm_shutdown can release what the
+// caller did not, and a later destroy call of a released handle is ignored.
+void register_handle(void *h, void (*destroy)(void *));
+bool unregister_handle(void *h);
 
 // ---- errors: negative status plus a thread-local message
 int64_t fail(int64_t code, const char *fmt, ...);

@@ -25,6 +25,7 @@ enum CtrlLine : int {
     L_BAR_CNT0,        // arrival counters of the counter barrier (64-bit), even and odd epochs
     L_BAR_CNT1,
     L_TAKE,            // multi-graph launch: the graph a group's block 0 took from the queue
+    L_INIT_CARD,       // |M| of the initial matching (64-bit), counted by the setup
     L_STAT0,           // stats counters (64-bit each, own lines)
     L_NLINES = L_STAT0 + 13
 };
@@ -74,6 +75,7 @@ struct DevGraph {
                              //        (F_MAXCLAIM; meaningful while the row is matched), or null
     uint32_t *ptrace = nullptr;  // [2 * kPhaseTrace] per phase: BFS levels, unmatched rows reached
                                  // (recorded with F_STATS), or null
+    int32_t *croot = nullptr;    // [nc]   F_LEVELS: root of the tree that reached each column, or null
 };
 
 // Options of one run, passed by value to the kernels.

@@ -365,7 +365,10 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
             st_i<S>(lo, mate);
             ne = make_int4(mate, root, adj.x, adj.y);
             newcol = true;
-            if (flags & F_LEVELS) g.clevel[mate] = level + 1;
+            if (flags & F_LEVELS) {
+                g.clevel[mate] = level + 1;
+                if (g.croot) g.croot[mate] = root;
+            }
         } else {
             st_i<S>(lo, -2);
             if ((flags & F_WR) && (flags & F_ENDPOINT)) {
@@ -392,7 +395,10 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
             if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
             ne = make_int4(mate, root, b, e);
             newcol = true;
-            if (flags & F_LEVELS) g.clevel[mate] = level + 1;
+            if (flags & F_LEVELS) {
+                g.clevel[mate] = level + 1;
+                if (g.croot) g.croot[mate] = root;
+            }
         }
     } else if (mate == -1) {
         if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | 0xFFFFFFFEull)) {
@@ -678,7 +684,10 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
             const bool in = c < nc, un = in && cm[u] == -1;
             const bool p = un && en[u] > b[u];
             const int4 e = make_int4((int)c, (int)c, b[u], en[u]);
-            if ((flags & F_LEVELS) && in) g.clevel[c] = un ? 0 : -1;
+            if ((flags & F_LEVELS) && in) {
+                g.clevel[c] = un ? 0 : -1;
+                if (g.croot) g.croot[c] = un ? (int)c : -1;
+            }
             if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
             push_entry(p, e, o.split, st, q);
         }
@@ -1243,17 +1252,24 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, Acc &acc,
 // ---------------------------------------------------------------------
 // Kernels
 
-// Copy the initial matching into the working state, reset stamps, control
-// block and barrier flags.
+// Copy the initial matching into the working state, reset stamps and
+// barrier flags, and count the initial matching's columns into the
+// control block's L_INIT_CARD (which launch_zero_ctrl cleared before).
 __global__ void k_setup(DevGraph g, const int32_t *init_c, const int32_t *init_r, uint32_t *ctrl, uint32_t *bar,
                         uint32_t flags)
 {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nt = gridDim.x * blockDim.x;
+    uint64_t m0 = 0;
     for (uint32_t c = tid; c < (uint32_t)g.nc; c += nt) {
-        g.cmatch[c] = init_c ? init_c[c] : -1;
+        const int r = init_c ? init_c[c] : -1;
+        g.cmatch[c] = r;
+        m0 += r >= 0;
         g.cdone[c] = 0;
-        if (flags & F_LEVELS) g.clevel[c] = -1;
+        if (flags & F_LEVELS) {
+            g.clevel[c] = -1;
+            if (g.croot) g.croot[c] = -1;
+        }
     }
     if (flags & F_DEFER)
         for (uint64_t i = tid; i < 2 * g.qcap; i += nt) g.fq0[i] = make_int4(-1, -1, -1, -1);
@@ -1263,14 +1279,17 @@ __global__ void k_setup(DevGraph g, const int32_t *init_c, const int32_t *init_r
         if (flags & F_LEVELS) g.pred[r] = -1;
         if (flags & F_MAXCLAIM) g.radj[r] = m >= 0 ? make_int2(g.colptr[m], g.colptr[m + 1]) : make_int2(0, 0);
     }
-    for (uint32_t i = tid; i < (uint32_t)(L_NLINES * kLineWords); i += nt) ctrl[i] = 0;
     if (bar)
         for (uint32_t i = tid; i < (uint32_t)(kMaxGridBlocks * kLineWords); i += nt) bar[i] = 0;
+    block_add(m0, reinterpret_cast<uint64_t *>(line(ctrl, L_INIT_CARD)));
 }
 
-// Optional input validation (option validate=1).
-__global__ void k_validate(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind, const int32_t *init_c,
-                           const int32_t *init_r, uint32_t *ctrl)
+// Optional input validation (option validate=1), in two launches: the CSC
+// structure first; the initial matching only once the structure is known to
+// be sound, because checking that a matched pair is an edge scans the
+// column's range of rowind, which a malformed colptr would put out of
+// bounds.
+__global__ void k_validate_csc(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind, uint32_t *ctrl)
 {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nt = gridDim.x * blockDim.x;
@@ -1280,7 +1299,15 @@ __global__ void k_validate(int32_t nc, int32_t nr, const int32_t *colptr, const 
     const int64_t nnz = colptr[nc];
     for (int64_t j = tid; j < nnz; j += nt)
         if (rowind[j] < 0 || rowind[j] >= nr) set_status(ctrl, kEInval);
-    if (!init_c) return;
+}
+
+// Runs after k_validate_csc left the status at 0: colptr starts at 0 and
+// never decreases, so every [colptr[c], colptr[c+1]) lies in [0, nnz).
+__global__ void k_validate_init(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind,
+                                const int32_t *init_c, const int32_t *init_r, uint32_t *ctrl)
+{
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nt = gridDim.x * blockDim.x;
     for (uint32_t c = tid; c < (uint32_t)nc; c += nt) {
         const int r = init_c[c];
         if (r == -1) continue;
@@ -1585,13 +1612,23 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
         g.fq1 = d.fq + d.nc;
         g.ends = d.ends;
         g.clevel = nullptr;
+        if (threadIdx.x == 0) s_m = 0;
+        __syncthreads();
+        uint32_t m0 = 0;
         for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
-            g.cmatch[c] = d.init_c ? d.init_c[c] : -1;
+            const int r = d.init_c ? d.init_c[c] : -1;
+            g.cmatch[c] = r;
+            m0 += r >= 0;
             g.cdone[c] = 0;
         }
         for (int r = threadIdx.x; r < g.nr; r += blockDim.x)
             g.rw[r] = (uint64_t)(uint32_t)(d.init_r ? d.init_r[r] : -1);
-        if (threadIdx.x == 0) s_m = 0;
+        if (m0) atomicAdd(&s_m, m0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (s_m) atomicAdd((unsigned long long *)line(ctrl, L_INIT_CARD), (unsigned long long)s_m);
+            s_m = 0;
+        }
         __syncthreads();
         uint32_t ph = 0, lv = 0;
         const bool ok = (g.nc > 0 && g.nr > 0) ? run_block<WAVE>(g, ctrl, o, acc, st, s_tmp, s_loc, &ph, &lv) : true;
@@ -1674,15 +1711,26 @@ hipError_t launch_zero_ctrl(uint32_t *ctrl, hipStream_t st)
 hipError_t launch_setup(const DevGraph &g, const int32_t *ic, const int32_t *ir, uint32_t *ctrl, uint32_t *bar,
                         uint32_t flags, hipStream_t st)
 {
+    // the control block is cleared first: k_setup counts into it
+    hipLaunchKernelGGL(k_zero_ctrl, dim3(1), dim3(256), 0, st, ctrl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int64_t n = g.nc > g.nr ? g.nc : g.nr;
     hipLaunchKernelGGL(k_setup, dim3(clamp_blocks(n, 256, 256, 8192)), dim3(256), 0, st, g, ic, ir, ctrl, bar, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_validate(int32_t nc, int32_t nr, const int32_t *cp, const int32_t *ri, const int32_t *ic,
-                           const int32_t *ir, uint32_t *ctrl, hipStream_t st)
+hipError_t launch_validate_csc(int32_t nc, int32_t nr, const int32_t *cp, const int32_t *ri, uint32_t *ctrl,
+                               hipStream_t st)
 {
-    hipLaunchKernelGGL(k_validate, dim3(1024), dim3(256), 0, st, nc, nr, cp, ri, ic, ir, ctrl);
+    hipLaunchKernelGGL(k_validate_csc, dim3(1024), dim3(256), 0, st, nc, nr, cp, ri, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_init(int32_t nc, int32_t nr, const int32_t *cp, const int32_t *ri, const int32_t *ic,
+                                const int32_t *ir, uint32_t *ctrl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_validate_init, dim3(1024), dim3(256), 0, st, nc, nr, cp, ri, ic, ir, ctrl);
     return hipGetLastError();
 }
 

@@ -373,17 +373,28 @@ void worker_loop(mcm_server *s)
             for (auto &sl : s->slots)
                 if (!sl.busy) { free_slot = &sl; break; }
             if (!free_slot) break;
+            // the multi-graph launch is cooperative: it waits (the requests
+            // stay ready) while another owner's cooperative launch is in
+            // flight; the gate is left when this launch's slot completes
+            if (!coop_gate().try_enter(s->compute)) break;
             std::vector<Request *> take;
             while (!s->big_ready.empty() && (int)take.size() < s->multi_max) {
                 take.push_back(s->big_ready.front());
                 s->big_ready.pop_front();
             }
-            if (launch_multi_reqs(s, *free_slot, take)) s->status = MCM_EHIP;
+            if (launch_multi_reqs(s, *free_slot, take)) {
+                s->status = MCM_EHIP;
+                if (!free_slot->busy) {  // nothing in flight under the gate for this slot
+                    (void)hipStreamSynchronize(s->compute);
+                    coop_gate().leave(s->compute);
+                }
+            }
             progressed = true;
         }
         // finished batched launches: their cards become known
         for (auto &sl : s->slots) {
             if (sl.busy && hipEventQuery(sl.done) == hipSuccess) {
+                if (sl.ngroups > 0) coop_gate().leave(s->compute);
                 for (int k = 0; k < std::max(sl.ngroups, 1); ++k)
                     if (*ctrl_line(sl.h_ctrl + (size_t)k * L_NLINES * kLineWords, L_STATUS) != 0)
                         s->status = MCM_EINTERNAL;
@@ -414,6 +425,34 @@ void worker_loop(mcm_server *s)
 }
 
 }  // namespace
+
+// Stops the worker and releases everything the server holds.
+static void server_free(mcm_server *s)
+{
+    s->stop.store(true);
+    s->cv.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipStreamSynchronize(s->compute);
+    (void)hipStreamSynchronize(s->copy);
+    // multi-graph launches still counted in the gate have completed now
+    for (auto &sl : s->slots)
+        if (sl.busy && sl.ngroups > 0) coop_gate().leave(s->compute);
+    for (auto &kv : s->live) {
+        Request *r = kv.second;
+        if (r->ev_in) (void)hipEventDestroy(r->ev_in);
+        if (r->ev_out) (void)hipEventDestroy(r->ev_out);
+        delete r;
+    }
+    for (auto &sl : s->slots) {
+        for (void *q : {(void *)sl.d_desc, (void *)sl.d_card, (void *)sl.d_ctrl, (void *)sl.d_bar}) if (q) (void)hipFree(q);
+        for (void *q : {(void *)sl.h_desc, (void *)sl.h_card, (void *)sl.h_ctrl}) if (q) (void)hipHostFree(q);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    if (s->compute) (void)hipStreamDestroy(s->compute);
+    if (s->copy) (void)hipStreamDestroy(s->copy);
+    s->arena.release();
+    delete s;
+}
 
 extern "C" {
 
@@ -470,6 +509,7 @@ int64_t mcm_server_create(int64_t hbm_budget_bytes, int32_t max_batch, mcm_serve
     s->st.budget_bytes = hbm_budget_bytes;
     s->t0 = Clock::now();
     s->worker = std::thread(worker_loop, s);
+    register_handle(s, [](void *h) { server_free(static_cast<mcm_server *>(h)); });
     *out = s;
     return MCM_OK;
 }
@@ -559,27 +599,8 @@ int mcm_server_stats_get(mcm_server *s, mcm_server_stats *out)
 
 int mcm_server_destroy(mcm_server *s)
 {
-    if (!s) return MCM_OK;
-    s->stop.store(true);
-    s->cv.notify_all();
-    if (s->worker.joinable()) s->worker.join();
-    (void)hipStreamSynchronize(s->compute);
-    (void)hipStreamSynchronize(s->copy);
-    for (auto &kv : s->live) {
-        Request *r = kv.second;
-        if (r->ev_in) (void)hipEventDestroy(r->ev_in);
-        if (r->ev_out) (void)hipEventDestroy(r->ev_out);
-        delete r;
-    }
-    for (auto &sl : s->slots) {
-        for (void *q : {(void *)sl.d_desc, (void *)sl.d_card, (void *)sl.d_ctrl, (void *)sl.d_bar}) if (q) (void)hipFree(q);
-        for (void *q : {(void *)sl.h_desc, (void *)sl.h_card, (void *)sl.h_ctrl}) if (q) (void)hipHostFree(q);
-        if (sl.done) (void)hipEventDestroy(sl.done);
-    }
-    if (s->compute) (void)hipStreamDestroy(s->compute);
-    if (s->copy) (void)hipStreamDestroy(s->copy);
-    s->arena.release();
-    delete s;
+    // a server that mcm_shutdown already released is not freed twice
+    if (s && unregister_handle(s)) server_free(s);
     return MCM_OK;
 }
 

@@ -7,6 +7,7 @@ fallback exists).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -64,7 +65,7 @@ EXPORTS = ["mcm_match", "mcm_match_batched", "mcm_konig_cover", "mcm_bfs_levels"
            "mcm_cheap_init", "mcm_batch_plan_create", "mcm_batch_plan_run", "mcm_batch_plan_info",
            "mcm_batch_plan_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
            "mcm_server_stats_get", "mcm_server_destroy", "mcm_set_option", "mcm_get_option", "mcm_last_stats",
-           "mcm_last_phases", "mcm_strerror", "mcm_version"]
+           "mcm_last_phases", "mcm_strerror", "mcm_version", "mcm_shutdown", "mcm_bfs_forest"]
 
 _lib = None
 
@@ -86,6 +87,8 @@ def lib():
     L.mcm_konig_cover.restype = i64
     L.mcm_bfs_levels.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
     L.mcm_bfs_levels.restype = i64
+    L.mcm_bfs_forest.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.mcm_bfs_forest.restype = i64
     L.mcm_cheap_init_host.argtypes = [i32, i32, vp, vp, vp, vp]
     L.mcm_cheap_init_host.restype = i64
     L.mcm_cheap_init.argtypes = [i32, i32, vp, vp, vp, vp, vp]
@@ -121,7 +124,13 @@ def lib():
     L.mcm_strerror.restype = ctypes.c_char_p
     L.mcm_version.argtypes = []
     L.mcm_version.restype = ctypes.c_char_p
+    L.mcm_shutdown.argtypes = []
+    L.mcm_shutdown.restype = ctypes.c_int
     _lib = L
+    # release the library's device memory, pinned buffers, events, live
+    # plans and servers while the HIP runtime is still up (before the
+    # interpreter and the runtime tear down)
+    atexit.register(L.mcm_shutdown)
     return L
 
 
@@ -257,6 +266,20 @@ def bfs_levels(dg: DeviceGraph, cmatch, rmatch, stream=None):
     f = _check(lib().mcm_bfs_levels(dg.nc, dg.nr, _ptr(dg.colptr), _ptr(dg.rowind), _ptr(cmatch), _ptr(rmatch),
                                     _ptr(cl), _ptr(rp), _stream(stream)))
     return f, cl, rp
+
+
+def bfs_forest(dg: DeviceGraph, cmatch, rmatch, stream=None):
+    """mcm_bfs_forest; returns (ends, col_level, col_root, row_pred), ends
+    being the unmatched rows reached that Alternate would start from."""
+    import torch
+    dev = dg.colptr.device
+    cl = torch.empty(dg.nc, dtype=torch.int32, device=dev)
+    cr = torch.empty(dg.nc, dtype=torch.int32, device=dev)
+    rp = torch.empty(dg.nr, dtype=torch.int32, device=dev)
+    en = torch.empty(max(dg.nr, 1), dtype=torch.int32, device=dev)
+    n = _check(lib().mcm_bfs_forest(dg.nc, dg.nr, _ptr(dg.colptr), _ptr(dg.rowind), _ptr(cmatch), _ptr(rmatch),
+                                    _ptr(cl), _ptr(cr), _ptr(rp), _ptr(en), _stream(stream)))
+    return en[:n], cl, cr, rp
 
 
 @dataclass

@@ -498,3 +498,81 @@ def test_phase_record(name, driver, loop):
     _set(stats=0)
     _gpu(g, certify=False)
     assert len(mcm.last_phases()[0]) == 0
+
+
+def test_validation_rejects_malformed_colptr_before_the_init_check():
+    """With validate=1 a malformed colptr is reported as MCM_EINVAL, and the
+    check of the initial matching (which scans column ranges of rowind) is
+    not run on it.  Every colptr value stays within [0, nnz], so the
+    structural check itself reads only inside the arrays."""
+    _set(validate=1)
+    g = gg.workload("grid64")
+    _, cm0, rm0 = mcm.cheap_init_host(g.colptr, g.rowind, g.nr)
+    icm, irm = torch.from_numpy(cm0).cuda(), torch.from_numpy(rm0).cuda()
+    ri = torch.from_numpy(g.rowind).cuda()
+    c = g.nc // 2
+    bad = g.colptr.copy()
+    bad[c] = bad[c + 1] + 1                      # colptr[c] > colptr[c + 1]: decreasing
+    assert 0 <= bad[c] <= g.nnz
+    shifted = g.colptr.copy()
+    shifted[0] = 1                               # colptr[0] != 0
+    for cp in (bad, shifted):
+        dgb = mcm.DeviceGraph(g.nc, g.nr, torch.from_numpy(cp).cuda(), ri)
+        for thr in (1 << 30, 0):                 # one-workgroup and persistent paths
+            _set(wg_threshold=thr)
+            for init in ((icm, irm), (None, None)):
+                with pytest.raises(mcm.McmError) as e:
+                    mcm.match(dgb, *init)
+                assert e.value.code == mcm.MCM_EINVAL
+    _set(wg_threshold=16384)
+    assert mcm.match(mcm.to_device(g), icm, irm)[0] == _oracle_card(g)
+
+
+# ------------------------------------------------------------------ rows in any order, duplicates
+def _shuffled_with_duplicates(g, seed, dup=0.1):
+    """The same pattern with each column's rows shuffled and about `dup` of
+    the entries stored twice (at random places of their column)."""
+    rng = np.random.default_rng(seed)
+    cols = []
+    for c in range(g.nc):
+        rows = g.rowind[g.colptr[c]:g.colptr[c + 1]].copy()
+        if len(rows):
+            extra = rows[rng.random(len(rows)) < dup]
+            rows = np.concatenate([rows, extra])
+            rng.shuffle(rows)
+        cols.append(rows)
+    colptr = np.zeros(g.nc + 1, np.int32)
+    colptr[1:] = np.cumsum([len(r) for r in cols])
+    rowind = np.concatenate(cols).astype(np.int32) if g.nnz else np.zeros(0, np.int32)
+    return gg.Graph(g.nc, g.nr, colptr, rowind, g.name + "_shuf_dup")
+
+
+@pytest.mark.parametrize("name", ["uniform2000", "grid128", "rmat13"])
+def test_unsorted_rows_and_duplicates(name):
+    """include/mcm.h allows rows of a column in any order and duplicated:
+    every launch form (one workgroup, persistent device loop with either row
+    claim, host loop, batched, the multi-graph launch) reaches the oracle's
+    |M| on such input, with a valid matching certified by the Konig cover."""
+    g0 = gg.workload(name)
+    g = _shuffled_with_duplicates(g0, 11)
+    assert g.nnz > g0.nnz and O.check_csc(g)
+    ref = _oracle_card(g)
+    assert ref == _oracle_card(g0)                # the same graph
+    forms = [dict(wg_threshold=1 << 30), dict(wg_threshold=0, loop="device", claim="max"),
+             dict(wg_threshold=0, loop="device", claim="probe", flush="atomic"),
+             dict(wg_threshold=0, loop="host"), dict(wg_threshold=0, loop="device", alternate="classic")]
+    for f in forms:
+        _set(**f)
+        for init in ("cheap", "empty"):
+            assert _gpu(g, init)[0] == (ref if init == "cheap" else _oracle_card(g, "empty")), (f, init)
+        for k, v in DEFAULTS.items():
+            mcm.set_option(k, v)
+    # batched: the graph twice, once through the workgroup kernel and once
+    # through the multi-graph launch
+    b = mcm.pack_batch([g, g0])
+    for thr in (1 << 40, 1):
+        _set(multi_threshold=thr)
+        total, cards, cm, rm = mcm.match_batched(b)
+        assert cards.tolist() == [_oracle_card(g, "empty")] * 2
+        assert O.check_matching(g, cm[:g.nc].cpu().numpy(), rm[:g.nr].cpu().numpy()) == cards[0]
+    _set(multi_threshold=1 << 15)
