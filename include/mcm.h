@@ -468,6 +468,8 @@ typedef struct {
     int32_t flush;           /* grid levels: 0 = queue atomic, 1 = deferred (counter barrier) */
     int32_t wr_check;        /* GPUBFS-WR root test: 0 = before the scan, 1 = beside each edge visit */
     int32_t alternate;       /* Alternate: 0 = classic, 1 = along the rows recorded at the claims */
+    int64_t pass_bytes;      /* per-phase passes under the fixed byte model (stats=1): 4 B and 1/8 B per
+                                column the root scan reads, 8 B per row FixMatching reads */
 } mcm_stats;
 
 int mcm_last_stats(mcm_stats *out);

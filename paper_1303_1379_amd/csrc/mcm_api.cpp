@@ -371,6 +371,7 @@ void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int l
     s.alt_steps = (int64_t)ctrl_stat(hc, S_ALT);
     s.fix_resets = (int64_t)ctrl_stat(hc, S_FIX);
     s.claims_tried = (int64_t)ctrl_stat(hc, S_TRIES);
+    s.pass_bytes = (int64_t)ctrl_stat(hc, S_PASS);
     s.roots = (int64_t)ctrl_stat(hc, S_ROOTS);
     s.t_expand_ms = (double)ctrl_stat(hc, S_T_EXPAND) / clock_khz;
     s.t_flush_ms = (double)ctrl_stat(hc, S_T_FLUSH) / clock_khz;

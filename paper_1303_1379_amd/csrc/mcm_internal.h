@@ -27,7 +27,7 @@ enum CtrlLine : int {
     L_TAKE,            // multi-graph launch: the graph a group's block 0 took from the queue
     L_INIT_CARD,       // |M| of the initial matching (64-bit), counted by the setup
     L_STAT0,           // stats counters (64-bit each, own lines)
-    L_NLINES = L_STAT0 + 13
+    L_NLINES = L_STAT0 + 14
 };
 constexpr int kLineWords = 32;        // 128 B / 4 B
 constexpr int kPhaseTrace = 4096;     // phases whose (levels, ends) a stats run records
@@ -35,6 +35,8 @@ constexpr int kMaxGridBlocks = 2048;  // arrival flags of the grid barrier, one 
 
 enum StatIdx : int {
     S_EDGES = 0, S_EXPANDED, S_CLAIMED, S_FOUND, S_ALT, S_FIX, S_ROOTS, S_TRIES,
+    S_PASS,      // bytes of the per-phase passes under the fixed byte model: 4 per column and 1/8 per
+                 // column (visit reset) of the root scan, 8 per row of FixMatching
     S_T_EXPAND, S_T_FLUSH, S_T_BARRIER, S_T_SMALL, S_T_AUGMENT  // wall-clock ticks seen by block 0 (stats=1)
 };
 

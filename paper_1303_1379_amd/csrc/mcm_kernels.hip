@@ -434,7 +434,7 @@ DEV void add_stat(uint64_t *stats, int idx, uint64_t v)
 // holds them through the run: a count is reduced over the wavefront and
 // added by its first lane (wavefront-uniform calls, all lanes active); the
 // timers (StatIdx S_T_*) are kept by thread 0.  Indices are StatIdx.
-constexpr int kAccN = 13;
+constexpr int kAccN = 14;
 
 struct Acc {
     uint64_t *c;  // LDS [kAccN]
@@ -1138,6 +1138,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         if (ph > o.max_phases) { if (leader) set_status(ctrl, kEInternal); return false; }
         const uint32_t lv0 = total_levels;
         init_roots(g, wave, nwaves, o, fc(0), st, s_tmp, acc);
+        if (timing && gr.b == 0) acc.tick(S_PASS, 4ull * (uint32_t)g.nc + (uint32_t)g.nc / 8);
         if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
         for (;;) {
             const int L = (int)s.L;
@@ -1191,6 +1192,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         alternate<kAgent>(g, ne, tid, nthreads, SINGLE ? flags : (flags & ~(uint32_t)F_FASTALT), ctrl, acc);
         if (!sync_all(none)) return false;
         fix_matching(g, tid, nthreads, flags, acc);
+        if (timing && gr.b == 0) acc.tick(S_PASS, 8ull * (uint32_t)g.nr);
         if ((flags & F_DEFER) && left.stop) {
             const QSink lq{(left.L & 1) ? g.fq1 : g.fq0, nullptr, nullptr, true};
             for (uint32_t i = tid; i < left.n; i += nthreads) put_entry(lq, i, make_int4(-1, -1, -1, -1));
@@ -1221,6 +1223,7 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, Acc &acc,
         if (threadIdx.x == 0) for (int i = 0; i < 5; ++i) s_loc[i] = 0;
         __syncthreads();
         init_roots(g, wave, nwaves, o, &s_loc[0], st, s_tmp, acc);
+        if (flags & F_STATS) acc.tick(S_PASS, 4ull * (uint32_t)g.nc + (uint32_t)g.nc / 8);
         int L = 0;
         for (;;) {
             const uint32_t n = *(volatile uint32_t *)&s_loc[L % 3];
@@ -1242,6 +1245,7 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, Acc &acc,
         alternate<kGroup>(g, ne, threadIdx.x, blockDim.x, flags & ~(uint32_t)F_FASTALT, ctrl, acc);
         __syncthreads();
         fix_matching(g, threadIdx.x, blockDim.x, flags, acc);
+        if (flags & F_STATS) acc.tick(S_PASS, 8ull * (uint32_t)g.nr);
     }
     __syncthreads();
     *ph_out = ph;
@@ -1483,6 +1487,7 @@ __global__ void k_init_roots(DevGraph g, uint32_t *ctrl, RunOpt o)
     __shared__ uint64_t s_acc[kAccN];
     Acc acc = make_acc(s_acc);
     init_roots(g, wave, nwaves, o, line(ctrl, L_FCOUNT0), st, stage_tmp(smem), acc);
+    if ((flags & F_STATS) && blockIdx.x == 0) acc.tick(S_PASS, 4ull * (uint32_t)g.nc + (uint32_t)g.nc / 8);
     if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
 }
 
@@ -1520,6 +1525,7 @@ __global__ void k_fix(DevGraph g, uint32_t *ctrl, uint32_t flags)
     __shared__ uint64_t s_acc[kAccN];
     Acc acc = make_acc(s_acc);
     fix_matching(g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, flags, acc);
+    if ((flags & F_STATS) && blockIdx.x == 0) acc.tick(S_PASS, 8ull * (uint32_t)g.nr);
     if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int i = 0; i < 3; ++i) { *line(ctrl, L_FCOUNT0 + i) = 0; *line(ctrl, L_FOUND0 + i) = 0; }

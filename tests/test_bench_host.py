@@ -37,6 +37,18 @@ def test_cpu_baseline_leg(bench):
     assert r["kind"] == "oracle" and r["cores"] == 1 and r["value"] > 0
     m = bench.cpu_model()
     assert m is None or isinstance(m, str)
+    # to the maximum: the oracle's own result, its edges read, graph edges per second
+    full = bench.cpu_baseline(g)
+    card, _, _, phases, edges = O.hopcroft_karp_ex(g, *O.cheap_init(g))
+    assert full["complete"] and full["card"] == card and full["phases"] == phases
+    assert full["graph_teps"] > 0 and str(edges) in full["sample"]
+
+
+def test_alg_bytes_model(bench):
+    s = dict(edges_scanned=10, cols_expanded=3, cols_claimed=2, rows_found=1, alt_steps=4, roots=5, pass_bytes=100)
+    assert bench.alg_bytes(s) == 8 * 10 + 16 * 3 + 16 * 2 + 12 + 20 * 4 + 4 * 5 + 100
+    r = bench.roofline(8e9, 0.5, "k")
+    assert r["achieved"] == 16.0 and r["frac"] == round(16.0 / 8000.0, 5) and r["bound"] == "hbm"
 
 
 def test_traffic_profile_lookup(bench):
