@@ -257,51 +257,51 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
 
 // Runs the phase loop on one graph whose state was set up by launch_setup.
 // flags decides APFB/APsB, WR, NOAUG.  Returns 0 or a negative status; the
-// control block is copied to w.h_ctrl (stream synchronised).
-int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t flags, hipStream_t st, int *loop_used)
+// control block is copied to b.h_ctrl (stream synchronised).
+int64_t run_graph(const RunBufs &b, const Options &o, const DevGraph &g, uint32_t flags, hipStream_t st, int *loop_used)
 {
     const bool wave = (flags & F_WAVE) != 0;
     int loop = o.loop;
     if (loop == 2) loop = 0;
     *loop_used = loop;
     if (loop != 0) flags &= ~(uint32_t)F_DEFER;  // deferred writes belong to the persistent level loop
-    RunOpt ro = run_opt(o, flags, g.nc, w.info);
+    RunOpt ro = run_opt(o, flags, g.nc, b.info);
     if (loop == 0) {
         int occ = 0;
         HIPCHK(persistent_occupancy(wave, o.block, &occ));
         if (occ < 1) return fail(MCM_EHIP, "persistent kernel cannot be resident with block %d", o.block);
         int per_cu = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
-        int blocks = w.info.ncu * per_cu;
+        int blocks = b.info.ncu * per_cu;
         if (o.max_blocks > 0 && blocks > o.max_blocks) blocks = o.max_blocks;
         if (blocks > kMaxGridBlocks) blocks = kMaxGridBlocks;
-        HIPCHK(hipEventRecord(w.ev0, st));
-        HIPCHK(launch_persistent(g, w.ctrl, w.bar, ro, wave, blocks, o.block, st));
-        HIPCHK(hipEventRecord(w.ev1, st));
-        HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
-        if ((flags & F_STATS) && g.ptrace)
-            HIPCHK(hipMemcpyAsync(w.h_ptrace, g.ptrace, sizeof(uint32_t) * 2 * kPhaseTrace, hipMemcpyDeviceToHost, st));
+        if (b.ev0) HIPCHK(hipEventRecord(b.ev0, st));
+        HIPCHK(launch_persistent(g, b.ctrl, b.bar, ro, wave, blocks, o.block, st));
+        if (b.ev1) HIPCHK(hipEventRecord(b.ev1, st));
+        HIPCHK(hipMemcpyAsync(b.h_ctrl, b.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+        if ((flags & F_STATS) && g.ptrace && b.h_ptrace)
+            HIPCHK(hipMemcpyAsync(b.h_ptrace, g.ptrace, sizeof(uint32_t) * 2 * kPhaseTrace, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         return 0;
     }
     // host-driven loop: one launch per step, control block read back after each level
-    uint32_t *hc = w.h_ctrl;
+    uint32_t *hc = b.h_ctrl;
     auto readback = [&]() -> int64_t {
-        HIPCHK(hipMemcpyAsync(hc, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hc, b.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         return 0;
     };
     uint32_t phases = 0, levels = 0, levels_before = 0;
     int64_t rc;
-    HIPCHK(hipEventRecord(w.ev0, st));
+    if (b.ev0) HIPCHK(hipEventRecord(b.ev0, st));
     for (uint32_t ph = 1;; ++ph) {
         if (ph > ro.max_phases) return fail(MCM_EINTERNAL, "phase bound exceeded");
-        HIPCHK(launch_init_roots(g, w.ctrl, ro, st));
+        HIPCHK(launch_init_roots(g, b.ctrl, ro, st));
         if ((rc = readback())) return rc;
         uint32_t n = *ctrl_line(hc, L_FCOUNT0);
         int L = 0;
         while (n > 0) {
             if ((uint32_t)L > ro.max_levels) return fail(MCM_EINTERNAL, "level bound exceeded");
-            HIPCHK(launch_level(g, w.ctrl, n, ph, L, ro, wave, w.info.ncu * 8, st));
+            HIPCHK(launch_level(g, b.ctrl, n, ph, L, ro, wave, b.info.ncu * 8, st));
             ++levels;
             if ((rc = readback())) return rc;
             if ((flags & F_APSB) && *ctrl_line(hc, L_FOUND0 + (L % 3))) break;
@@ -309,22 +309,22 @@ int64_t run_graph(Workspace &w, const Options &o, const DevGraph &g, uint32_t fl
             ++L;
         }
         const uint32_t ne = *ctrl_line(hc, L_NENDS);
-        if ((flags & F_STATS) && ph <= (uint32_t)kPhaseTrace) {
-            w.h_ptrace[2 * (ph - 1)] = levels - levels_before;
-            w.h_ptrace[2 * (ph - 1) + 1] = ne;
+        if ((flags & F_STATS) && b.h_ptrace && ph <= (uint32_t)kPhaseTrace) {
+            b.h_ptrace[2 * (ph - 1)] = levels - levels_before;
+            b.h_ptrace[2 * (ph - 1) + 1] = ne;
         }
         levels_before = levels;
         phases = ph;
         if (ne == 0 || (flags & F_NOAUG)) break;
-        HIPCHK(launch_alternate(g, w.ctrl, ne, flags, st));
-        HIPCHK(launch_fix(g, w.ctrl, flags, st));
+        HIPCHK(launch_alternate(g, b.ctrl, ne, flags, st));
+        HIPCHK(launch_fix(g, b.ctrl, flags, st));
     }
-    HIPCHK(hipEventRecord(w.ev1, st));
+    if (b.ev1) HIPCHK(hipEventRecord(b.ev1, st));
     // record counts in the device control block so both loops report alike
     hc[L_PHASE * kLineWords] = phases;
     hc[L_LEVELS * kLineWords] = levels;
-    HIPCHK(hipMemcpyAsync(ctrl_line(w.ctrl, L_PHASE), ctrl_line(hc, L_PHASE), 4, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ctrl_line(w.ctrl, L_LEVELS), ctrl_line(hc, L_LEVELS), 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctrl_line(b.ctrl, L_PHASE), ctrl_line(hc, L_PHASE), 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctrl_line(b.ctrl, L_LEVELS), ctrl_line(hc, L_LEVELS), 4, hipMemcpyHostToDevice, st));
     if ((rc = readback())) return rc;
     return 0;
 }
@@ -411,12 +411,10 @@ int64_t check_null_rowind(int32_t nc, int32_t nr, const int32_t *colptr, const i
 }
 
 // One workgroup matches one graph (small graphs).
-int64_t run_single_wg(Workspace &w, const Options &o, int32_t nc, int32_t nr, const int32_t *colptr,
+int64_t run_single_wg(const RunBufs &b, const Options &o, int32_t nc, int32_t nr, const int32_t *colptr,
                       const int32_t *rowind, const int32_t *ic, const int32_t *ir, int32_t *oc, int32_t *orr,
                       uint32_t flags, hipStream_t st)
 {
-    int64_t rc;
-    if ((rc = ensure_desc(w, 1))) return rc;
     BatchDesc d{};
     d.nc = nc;
     d.nr = nr;
@@ -426,23 +424,158 @@ int64_t run_single_wg(Workspace &w, const Options &o, int32_t nc, int32_t nr, co
     d.init_r = ir;
     d.out_c = oc;
     d.out_r = orr;
-    d.rw = w.rw;
-    d.pred = w.pred;
-    d.cdone = w.cdone;
-    d.fq = w.fq;
-    d.ends = w.ends;
-    w.h_desc[0] = d;
+    d.rw = b.rw;
+    d.pred = b.pred;
+    d.cdone = b.cdone;
+    d.fq = b.fq;
+    d.ends = b.ends;
+    *b.h_desc = d;
     HIPCHK(prepare_match_wg(o.wg_block));
-    HIPCHK(hipMemcpyAsync(w.desc, w.h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
-    HIPCHK(launch_zero_ctrl(w.ctrl, st));
-    RunOpt ro = run_opt(o, flags, nc, w.info);
+    HIPCHK(hipMemcpyAsync(b.desc, b.h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_zero_ctrl(b.ctrl, st));
+    RunOpt ro = run_opt(o, flags, nc, b.info);
     ro.split = 0;  // the graph's queue slices hold exactly nc entries
-    HIPCHK(hipEventRecord(w.ev0, st));
-    HIPCHK(launch_match_wg(w.desc, nullptr, 1, w.card, w.ctrl, ro, (flags & F_WAVE) != 0, 1, o.wg_block, st));
-    HIPCHK(hipEventRecord(w.ev1, st));
-    HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+    if (b.ev0) HIPCHK(hipEventRecord(b.ev0, st));
+    HIPCHK(launch_match_wg(b.desc, nullptr, 1, b.card, b.ctrl, ro, (flags & F_WAVE) != 0, 1, o.wg_block, st));
+    if (b.ev1) HIPCHK(hipEventRecord(b.ev1, st));
+    HIPCHK(hipMemcpyAsync(b.h_ctrl, b.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return 0;
+}
+
+// The row-claim and Alternate forms of one mcm_match run (see the options
+// claim, flush, wr_check and alternate); nnz < 0 when unknown.
+uint32_t match_flags(const Options &o, int32_t nc, int32_t nr, int64_t nnz, bool single_wg)
+{
+    uint32_t flags = base_flags(o, nc, 0);
+    // Atomic-maximum claims where rows have few edges: a row then has few
+    // visitors per phase and the atomic replaces a probe plus a
+    // compare-and-swap.  Hub rows (skewed degrees) keep the probe, which lets
+    // all but the first visitor of a level skip the atomic.
+    const bool low_degree = nnz >= 0 && nnz <= kMaxClaimDegree * (int64_t)nr;
+    if (!single_wg && (o.claim == 1 || (o.claim == 2 && low_degree))) flags |= F_MAXCLAIM;
+    // The WR root check: beside the edge visit on low-degree graphs (their
+    // long chains of small levels would wait for the root's load before the
+    // scan), before the scan on skewed ones (their large levels save the
+    // rowind loads of trees that are done).
+    if (!single_wg && o.wr_check == 2 && !low_degree) flags &= ~(uint32_t)F_WR_LATE;
+    // Persistent level loop with the counter barrier: a grid level's next
+    // frontier is reserved by the barrier's own addition, and grid levels
+    // pass their barriers without fences (what they share is in agent-scope
+    // atomics).  It pays where levels are many and small (low degree); on
+    // skewed graphs (few, large levels) the per-entry checks cost more.
+    if (!single_wg && o.bar_counter && o.loop != 1 && (o.flush == 1 || (o.flush == 2 && low_degree)))
+        flags |= F_DEFER;
+    // Alternate along recorded rows where walks are long (low-degree graphs:
+    // grid2048 430 -> 413 ms); on skewed graphs the extra load per entry
+    // and store per claim cost more than their short walks save, and without
+    // WR (many ends per tree) walks would repeat their shared ways.
+    if (!single_wg && (o.alternate == 1 || (o.alternate == 2 && low_degree && o.wr))) flags |= F_FASTALT;
+    return flags;
+}
+
+// One mcm_match run on state buffers `b` (sized for the graph and `flags`):
+// optional validation, then the one-workgroup kernel or setup, the phase
+// loop and finish.  Returns |M| or a negative status; records the stats.
+int64_t match_run(const RunBufs &b, const Options &o, uint32_t flags, bool single_wg, int32_t ncols, int32_t nrows,
+                  const int32_t *colptr, const int32_t *rowind, const int32_t *init_cmatch,
+                  const int32_t *init_rmatch, int32_t *out_cmatch, int32_t *out_rmatch, hipStream_t st,
+                  const void *owner)
+{
+    int64_t rc;
+    if (o.validate) {
+        // the structure first; the initial matching (whose on-edge check
+        // scans column ranges of rowind) only on a sound structure
+        auto status = [&]() -> int64_t {
+            HIPCHK(hipMemcpyAsync(b.h_ctrl, b.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            return (int32_t)*ctrl_line(b.h_ctrl, L_STATUS);
+        };
+        HIPCHK(launch_zero_ctrl(b.ctrl, st));
+        HIPCHK(launch_validate_csc(ncols, nrows, colptr, rowind, b.ctrl, st));
+        int64_t s = status();
+        if (s == MCM_EINVAL) return fail(MCM_EINVAL, "malformed CSC input");
+        if (s < 0) return s;
+        if (init_cmatch) {
+            HIPCHK(launch_validate_init(ncols, nrows, colptr, rowind, init_cmatch, init_rmatch, b.ctrl, st));
+            s = status();
+            if (s == MCM_EBADINIT) return fail(MCM_EBADINIT, "initial matching is inconsistent or not on edges");
+            if (s < 0) return s;
+        }
+    }
+    int loop = 0;
+    float ms = 0.f;
+    if (single_wg) {
+        if ((rc = run_single_wg(b, o, ncols, nrows, colptr, rowind, init_cmatch, init_rmatch, out_cmatch, out_rmatch,
+                                flags, st)))
+            return rc;
+        if (b.ev0) HIPCHK(hipEventElapsedTime(&ms, b.ev0, b.ev1));
+        loop = 2;
+        const int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(b.h_ctrl, L_CARD));
+        const int32_t s = (int32_t)*ctrl_line(b.h_ctrl, L_STATUS);
+        const int64_t init_card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(b.h_ctrl, L_INIT_CARD));
+        record_stats(b.h_ctrl, init_card, card, ms, loop, flags, b.info.clock_khz);
+        record_phases(nullptr, 0);  // the one-workgroup path keeps no per-phase record
+        if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
+        return card;
+    }
+
+    DevGraph g;
+    g.colptr = colptr;
+    g.rowind = rowind;
+    g.nc = ncols;
+    g.nr = nrows;
+    g.cmatch = out_cmatch;
+    g.rw = b.rw;
+    g.pred = b.pred;
+    g.cdone = b.cdone;
+    g.fq0 = b.fq;
+    g.fq1 = b.fq + b.cap_q;
+    g.ends = b.ends;
+    g.clevel = nullptr;
+    g.ptrace = (flags & F_STATS) ? b.ptrace : nullptr;
+    g.radj = (flags & F_MAXCLAIM) ? b.radj : nullptr;
+    g.prow = (flags & F_FASTALT) ? b.prow : nullptr;
+    g.qcap = b.cap_q;
+    CoopHold hold(owner, st);  // at most one cooperative launch in flight in the process
+    HIPCHK(launch_setup(g, init_cmatch, init_rmatch, b.ctrl, b.bar, flags, st));
+    if ((rc = run_graph(b, o, g, flags, st, &loop))) return rc;
+    HIPCHK(launch_finish(g, out_rmatch, b.ctrl, st));
+    HIPCHK(hipMemcpyAsync(b.h_ctrl, b.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (b.ev0) HIPCHK(hipEventElapsedTime(&ms, b.ev0, b.ev1));
+    const int32_t s = (int32_t)*ctrl_line(b.h_ctrl, L_STATUS);
+    const int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(b.h_ctrl, L_CARD));
+    const int64_t init_card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(b.h_ctrl, L_INIT_CARD));
+    record_stats(b.h_ctrl, init_card, card, ms, loop, flags, b.info.clock_khz);
+    record_phases((flags & F_STATS) && b.h_ptrace ? b.h_ptrace : nullptr, *ctrl_line(b.h_ctrl, L_PHASE));
+    if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
+    return card;
+}
+
+RunBufs bufs_of(Workspace &w)
+{
+    RunBufs b;
+    b.rw = w.rw;
+    b.pred = w.pred;
+    b.cdone = w.cdone;
+    b.fq = w.fq;
+    b.cap_q = w.cap_q;
+    b.ends = w.ends;
+    b.radj = w.radj;
+    b.prow = w.prow;
+    b.ctrl = w.ctrl;
+    b.bar = w.bar;
+    b.ptrace = w.ptrace;
+    b.desc = w.desc;
+    b.card = w.card;
+    b.h_ctrl = w.h_ctrl;
+    b.h_ptrace = w.h_ptrace;
+    b.h_desc = w.h_desc;
+    b.ev0 = w.ev0;
+    b.ev1 = w.ev1;
+    b.info = w.info;
+    return b;
 }
 
 }  // namespace host
@@ -709,107 +842,12 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
                                  : &nnz)))
         return rc;
     if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows, std::max(qcap, (size_t)ncols)))) return rc;
-
-    if (o.validate) {
-        // the structure first; the initial matching (whose on-edge check
-        // scans column ranges of rowind) only on a sound structure
-        auto status = [&]() -> int64_t {
-            HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            return (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
-        };
-        HIPCHK(launch_zero_ctrl(w.ctrl, st));
-        HIPCHK(launch_validate_csc(ncols, nrows, colptr, rowind, w.ctrl, st));
-        int64_t s = status();
-        if (s == MCM_EINVAL) return fail(MCM_EINVAL, "malformed CSC input");
-        if (s < 0) return s;
-        if (init_cmatch) {
-            HIPCHK(launch_validate_init(ncols, nrows, colptr, rowind, init_cmatch, init_rmatch, w.ctrl, st));
-            s = status();
-            if (s == MCM_EBADINIT) return fail(MCM_EBADINIT, "initial matching is inconsistent or not on edges");
-            if (s < 0) return s;
-        }
-    }
-
-    uint32_t flags = base_flags(o, ncols, 0);
-    // Atomic-maximum claims where rows have few edges: a row then has few
-    // visitors per phase and the atomic replaces a probe plus a
-    // compare-and-swap.  Hub rows (skewed degrees) keep the probe, which lets
-    // all but the first visitor of a level skip the atomic.
-    const bool low_degree = nnz >= 0 && nnz <= kMaxClaimDegree * (int64_t)nrows;
-    if (!single_wg && (o.claim == 1 || (o.claim == 2 && low_degree))) flags |= F_MAXCLAIM;
-    // The WR root check: beside the edge visit on low-degree graphs (their
-    // long chains of small levels would wait for the root's load before the
-    // scan), before the scan on skewed ones (their large levels save the
-    // rowind loads of trees that are done).
-    if (!single_wg && o.wr_check == 2 && !low_degree) flags &= ~(uint32_t)F_WR_LATE;
-    // Persistent level loop with the counter barrier: a grid level's next
-    // frontier is reserved by the barrier's own addition, and grid levels
-    // pass their barriers without fences (what they share is in agent-scope
-    // atomics).  It pays where levels are many and small (low degree); on
-    // skewed graphs (few, large levels) the per-entry checks cost more.
-    if (!single_wg && o.bar_counter && o.loop != 1 && (o.flush == 1 || (o.flush == 2 && low_degree)))
-        flags |= F_DEFER;
-    int loop = 0;
-    float ms = 0.f;
-    int64_t init_card = -1;
-    if (single_wg) {
-        if ((rc = run_single_wg(w, o, ncols, nrows, colptr, rowind, init_cmatch, init_rmatch, out_cmatch, out_rmatch,
-                                flags, st)))
-            return rc;
-        HIPCHK(hipEventElapsedTime(&ms, w.ev0, w.ev1));
-        loop = 2;
-        int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
-        int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
-        init_card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_INIT_CARD));
-        record_stats(w.h_ctrl, init_card, card, ms, loop, flags, w.info.clock_khz);
-        record_phases(nullptr, 0);  // the one-workgroup path keeps no per-phase record
-        if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
-        return card;
-    }
-
-    DevGraph g;
-    g.colptr = colptr;
-    g.rowind = rowind;
-    g.nc = ncols;
-    g.nr = nrows;
-    g.cmatch = out_cmatch;
-    g.rw = w.rw;
-    g.pred = w.pred;
-    g.cdone = w.cdone;
-    g.fq0 = w.fq;
-    g.fq1 = w.fq + w.cap_q;
-    g.ends = w.ends;
-    g.clevel = nullptr;
-    g.ptrace = (flags & F_STATS) ? w.ptrace : nullptr;
-    if (flags & F_MAXCLAIM) {
-        if ((rc = ensure_radj(w, (size_t)nrows))) return rc;
-        g.radj = w.radj;
-    }
-    g.qcap = w.cap_q;
-    // Alternate along recorded rows where walks are long (low-degree graphs:
-    // grid2048 430 -> 413 ms); on skewed graphs the extra load per entry
-    // and store per claim cost more than their short walks save, and without
-    // WR (many ends per tree) walks would repeat their shared ways.
-    if (o.alternate == 1 || (o.alternate == 2 && low_degree && o.wr)) {
-        if ((rc = ensure_prow(w, (size_t)nrows))) return rc;
-        g.prow = w.prow;
-        flags |= F_FASTALT;
-    }
-    CoopHold hold(stream, st);  // at most one cooperative launch in flight in the process
-    HIPCHK(launch_setup(g, init_cmatch, init_rmatch, w.ctrl, w.bar, flags, st));
-    if ((rc = run_graph(w, o, g, flags, st, &loop))) return rc;
-    HIPCHK(launch_finish(g, out_rmatch, w.ctrl, st));
-    HIPCHK(hipMemcpyAsync(w.h_ctrl, w.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipEventElapsedTime(&ms, w.ev0, w.ev1));
-    const int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
-    const int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_CARD));
-    init_card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(w.h_ctrl, L_INIT_CARD));
-    record_stats(w.h_ctrl, init_card, card, ms, loop, flags, w.info.clock_khz);
-    record_phases((flags & F_STATS) ? w.h_ptrace : nullptr, *ctrl_line(w.h_ctrl, L_PHASE));
-    if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
-    return card;
+    if (single_wg && (rc = ensure_desc(w, 1))) return rc;
+    const uint32_t flags = match_flags(o, ncols, nrows, nnz, single_wg);
+    if ((flags & F_MAXCLAIM) && (rc = ensure_radj(w, (size_t)nrows))) return rc;
+    if ((flags & F_FASTALT) && (rc = ensure_prow(w, (size_t)nrows))) return rc;
+    return match_run(bufs_of(w), o, flags, single_wg, ncols, nrows, colptr, rowind, init_cmatch, init_rmatch,
+                     out_cmatch, out_rmatch, st, stream);
 }
 
 // Shared by mcm_konig_cover, mcm_bfs_levels and mcm_bfs_forest: one
@@ -860,7 +898,7 @@ static int64_t one_bfs_phase(Workspace &w, const Options &o, int32_t nc, int32_t
     HIPCHK(launch_setup(g, cm, rm, w.ctrl, w.bar, flags, st));
     int loop = 0;
     Options oo = o;
-    if ((rc = run_graph(w, oo, g, flags, st, &loop))) return rc;
+    if ((rc = run_graph(bufs_of(w), oo, g, flags, st, &loop))) return rc;
     const int32_t s = (int32_t)*ctrl_line(w.h_ctrl, L_STATUS);
     if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
     *gout = g;

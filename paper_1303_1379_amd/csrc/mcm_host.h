@@ -152,6 +152,30 @@ struct Workspace {
     DevInfo info;
 };
 
+// Where one match keeps its state and reads its results back: the
+// per-device workspace (mcm_match), or slices of the static scratch array
+// with plain host memory (mcm_match_noalloc).
+struct RunBufs {
+    uint64_t *rw = nullptr;
+    int32_t *pred = nullptr;
+    uint32_t *cdone = nullptr;
+    int4 *fq = nullptr;          // two frontier queues: fq and fq + cap_q
+    size_t cap_q = 0;
+    int32_t *ends = nullptr;
+    int2 *radj = nullptr;        // atomic-maximum claims only
+    int32_t *prow = nullptr;     // recorded-row Alternate only
+    uint32_t *ctrl = nullptr;    // control block [L_NLINES lines]
+    uint32_t *bar = nullptr;     // [kMaxGridBlocks lines]
+    uint32_t *ptrace = nullptr;  // [2 * kPhaseTrace] (stats runs), or null
+    BatchDesc *desc = nullptr;   // one descriptor (one-workgroup path)
+    int64_t *card = nullptr;     // one count (one-workgroup path)
+    uint32_t *h_ctrl = nullptr;  // host copy of the control block
+    uint32_t *h_ptrace = nullptr;  // host copy of the phase record, or null
+    BatchDesc *h_desc = nullptr;   // host staging of the descriptor
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timing, or none
+    DevInfo info;
+};
+
 Workspace &workspace(int dev);
 std::mutex &workspace_mutex();
 int64_t ensure_base(Workspace &w, int dev);
