@@ -444,6 +444,19 @@ def test_batched_empty_members_and_no_init():
 
 
 # ------------------------------------------------------------------ full-size workloads (as timed by bench.py)
+def _full_size_card(g, name):
+    """The oracle's |M| of a full-size workload, stored by
+    tests/golden/make_full_size_cards.py, after checking that the stored
+    input is the one generated here (size and FNV-1a hash)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "full_size_cards.txt")
+    with open(path) as f:
+        rows = {ln.split()[0]: ln.split() for ln in f if ln.strip() and not ln.startswith("#")}
+    w = rows[name]
+    assert (int(w[1]), int(w[2]), int(w[3]), int(w[4], 16)) == (g.nc, g.nr, g.nnz, g.fnv1a()), name
+    return int(w[6])
+
+
 @pytest.mark.parametrize("name", ["grid2048", "rmat23"])
 def test_full_size_certified(name):
     """Full size: oracle-free exact certificate.  The output must be a valid
@@ -451,7 +464,9 @@ def test_full_size_certified(name):
     proves it maximum by weak duality; for the grid the size must also lie in
     the closed-form window n - |Rdel u Cdel| <= nu <= n - ndel."""
     g = gg.workload(name)
+    ref = _full_size_card(g, name)
     card, cm, rm = _gpu(g)
+    assert card == ref
     if name == "grid2048":
         n = 2048 * 2048
         nd = int(np.floor(0.03 * n))
@@ -469,7 +484,7 @@ def test_full_size_other_forms(name, opts):
     that the defaults do not pick for them: a valid matching certified
     maximum by the GPU's Konig cover, the same size as with the defaults."""
     g = gg.workload(name)
-    ref, _, _ = _gpu(g)
+    ref = _full_size_card(g, name)
     _set(**opts)
     card, _, _ = _gpu(g)
     assert card == ref, opts
