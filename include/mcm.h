@@ -470,6 +470,7 @@ typedef struct {
     int32_t alternate;       /* Alternate: 0 = classic, 1 = along the rows recorded at the claims */
     int64_t pass_bytes;      /* per-phase passes under the fixed byte model (stats=1): 4 B and 1/8 B per
                                 column the root scan reads, 8 B per row FixMatching reads */
+    int32_t schedule;        /* BFS of mcm_match: 0 = level-synchronous, 1 = level-free */
 } mcm_stats;
 
 int mcm_last_stats(mcm_stats *out);

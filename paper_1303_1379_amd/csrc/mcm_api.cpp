@@ -387,6 +387,7 @@ void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int l
     s.flush = (flags & F_DEFER) && loop == 0 ? 1 : 0;
     s.wr_check = (flags & F_WR_LATE) ? 1 : 0;
     s.alternate = (flags & F_FASTALT) ? 1 : 0;
+    s.schedule = (flags & F_ASYNC) && loop == 0 ? 1 : 0;
     g_stats = s;
 }
 
@@ -471,6 +472,12 @@ uint32_t match_flags(const Options &o, int32_t nc, int32_t nr, int64_t nnz, bool
     // and store per claim cost more than their short walks save, and without
     // WR (many ends per tree) walks would repeat their shared ways.
     if (!single_wg && (o.alternate == 1 || (o.alternate == 2 && low_degree && o.wr))) flags |= F_FASTALT;
+    // Level-free BFS (APFB on the device loop only): no grid barrier between
+    // BFS levels; the deferred level forms do not apply then.
+    if (!single_wg && !o.apsb && o.loop != 1 && o.schedule != 0) {
+        flags |= F_ASYNC;
+        flags &= ~(uint32_t)F_DEFER;
+    }
     return flags;
 }
 
@@ -688,6 +695,11 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "defer") g_opt.flush = 1;
         else if (v == "auto") g_opt.flush = 2;
         else return (int)fail(MCM_EINVAL, "flush must be atomic, defer or auto");
+    } else if (k == "schedule") {
+        if (v == "levels") g_opt.schedule = 0;
+        else if (v == "async") g_opt.schedule = 1;
+        else if (v == "auto") g_opt.schedule = 2;
+        else return (int)fail(MCM_EINVAL, "schedule must be levels, async or auto");
     } else if (k == "claim") {
         if (v == "probe") g_opt.claim = 0;
         else if (v == "max") g_opt.claim = 1;
@@ -753,6 +765,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "barrier") v = o.bar_counter ? "counter" : "flags";
     else if (k == "endpoints") v = o.endpoints == 0 ? "all" : (o.endpoints == 1 ? "one" : "auto");
     else if (k == "claim") v = o.claim == 0 ? "probe" : (o.claim == 1 ? "max" : "auto");
+    else if (k == "schedule") v = o.schedule == 0 ? "levels" : (o.schedule == 1 ? "async" : "auto");
     else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
     else if (k == "local_levels") v = std::to_string(o.local_levels);
     else if (k == "alternate") v = o.alternate == 0 ? "classic" : (o.alternate == 1 ? "fast" : "auto");

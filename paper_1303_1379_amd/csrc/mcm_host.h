@@ -91,6 +91,7 @@ struct Options {
     int flush = 2;            // grid levels: 0 reserve by a queue atomic, 1 through the counter barrier, 2 auto (1)
     int local_levels = 6;     // grid levels: a wavefront expands its own new entries this many times more
     int alternate = 2;        // mcm_match's Alternate: 0 classic, 1 recorded rows, 2 auto (1 on low degree)
+    int schedule = 0;         // mcm_match's BFS: 0 level-synchronous, 1 level-free, 2 auto
     int mapping = 2;          // 0 thread, 1 wave, 2 auto
     int loop = 2;             // 0 device, 1 host, 2 auto
     bool validate = false;

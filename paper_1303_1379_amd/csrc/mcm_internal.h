@@ -26,6 +26,9 @@ enum CtrlLine : int {
     L_BAR_CNT1,
     L_TAKE,            // multi-graph launch: the graph a group's block 0 took from the queue
     L_INIT_CARD,       // |M| of the initial matching (64-bit), counted by the setup
+    L_AQ,              // level-free BFS: entries reserved (low 32 bits) and finished (high 32) in the
+                       // phase-long queue, one 64-bit word
+    L_AQ_TAKE,         // level-free BFS: entries taken from that queue
     L_STAT0,           // stats counters (64-bit each, own lines)
     L_NLINES = L_STAT0 + 14
 };
@@ -54,8 +57,11 @@ enum Flags : uint32_t {
     F_DEFER = 1024u,      // grid levels: frontier slots reserved by the counter barrier's own addition,
                           // entries written after arriving (agent-scope words, -1 once consumed);
                           // needs F_BAR_COUNTER and qcap
-    F_FASTALT = 2048u     // claims record the row behind the claiming column; Alternate follows it
+    F_FASTALT = 2048u,    // claims record the row behind the claiming column; Alternate follows it
                           // (two independent loads per step); needs prow
+    F_ASYNC = 4096u       // APFB: a phase's BFS without levels (one phase-long queue that every
+                          // wavefront takes entries from as they appear); needs qcap, excludes
+                          // F_APSB and F_LEVELS
 };
 
 // Device view of one graph plus its working state.

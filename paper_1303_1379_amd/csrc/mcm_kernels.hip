@@ -203,10 +203,12 @@ struct QSink {
     uint32_t *c32;
     uint64_t *c64;
     bool atomic;
+    uint64_t cap = 0;  // slots of q (0: not checked); the level-free BFS checks every write
 };
 
 DEV void put_entry(const QSink &k, uint32_t i, const int4 &e)
 {
+    if (k.cap && i >= k.cap) return;  // never reached: a phase reserves at most qcap slots
     if (k.atomic) {
         uint64_t *p = reinterpret_cast<uint64_t *>(k.q + i);
         __hip_atomic_store(p, (uint64_t)(uint32_t)e.x | ((uint64_t)(uint32_t)e.y << 32), __ATOMIC_RELAXED,
@@ -509,6 +511,89 @@ DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, const QSin
     }
 }
 
+// Expand one frontier entry per lane (lanes with `have`): visit its edges,
+// claim rows, stage the columns claimed and the unmatched rows reached.
+// Wavefront-uniform call.  `late`: the GPUBFS-WR root test beside each edge
+// visit (wave mapping), else before the scan.
+template <bool WAVE, int S>
+DEV void expand_entries(const DevGraph &g, const int4 e, const bool have, uint32_t ph, int level, uint32_t flags,
+                        bool late, const RunOpt &o, const LevelIO &io, Stage &st, Acc &acc, bool &any_end)
+{
+    const int lane = __lane_id();
+    int deg = 0;
+    uint32_t rdone = 0;
+    int cmate = -1;  // F_FASTALT: the entry column's mate (cmatch does not change during the BFS)
+    if (have) {
+        deg = e.w - e.z;
+        if (flags & F_FASTALT) cmate = g.cmatch[e.x];
+        if (late) rdone = ld_u<S>(&g.cdone[e.y]);
+        else if ((flags & F_WR) && deg > 0 && ld_u<S>(&g.cdone[e.y]) == ph) deg = 0;
+    }
+    if (flags & F_STATS) {
+        const bool live = !(late && rdone == ph);
+        acc.add(S_EDGES, live ? (uint64_t)deg : 0u);
+        acc.add(S_EXPANDED, (live && deg > 0) ? 1u : 0u);
+    }
+    if (WAVE) {
+        const int incl = wave_incl_scan(deg);
+        const int excl = incl - deg;
+        const int total = __shfl(incl, 63, 64);
+        for (int eb = 0; eb < total; eb += 64) {
+            const int k = eb + lane;
+            // owner lane: the largest o with excl[o] <= k (excl is non-decreasing)
+            int own = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const int v = __shfl(excl, own + step, 64);
+                if (v <= k) own += step;
+            }
+            const int ocol = __shfl(e.x, own, 64);
+            const int oroot = __shfl(e.y, own, 64);
+            const int obeg = __shfl(e.z, own, 64);
+            const int oexcl = __shfl(excl, own, 64);
+            // (every lane takes part in the shuffles: a lane may read an
+            // owner that has no edge of its own in this round)
+            const int omate = (flags & F_FASTALT) ? __shfl(cmate, own, 64) : -1;
+            bool newcol = false, newend = false, tried = false;
+            int4 ne = make_int4(0, 0, 0, 0);
+            int r = 0;
+            if (k < total) {
+                r = g.rowind[obeg + (k - oexcl)];
+                const uint32_t odone = late ? (uint32_t)__shfl((int)rdone, own, 64) : 0u;
+                if (!late || odone != ph)
+                    visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend, tried, omate);
+            }
+            push_entry(newcol, ne, o.split, st, io.next);
+            push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
+            any_end |= newend;
+            if (flags & F_STATS) {
+                acc.add(S_CLAIMED, newcol ? 1u : 0u);
+                acc.add(S_FOUND, newend ? 1u : 0u);
+                acc.add(S_TRIES, tried ? 1u : 0u);
+            }
+        }
+    } else {
+        const int maxdeg = wave_max(deg);
+        for (int t = 0; t < maxdeg; ++t) {
+            bool newcol = false, newend = false, tried = false;
+            int4 ne = make_int4(0, 0, 0, 0);
+            int r = 0;
+            if (t < deg) {
+                r = g.rowind[e.z + t];
+                visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend, tried, cmate);
+            }
+            push_entry(newcol, ne, o.split, st, io.next);
+            push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
+            any_end |= newend;
+            if (flags & F_STATS) {
+                acc.add(S_CLAIMED, newcol ? 1u : 0u);
+                acc.add(S_FOUND, newend ? 1u : 0u);
+                acc.add(S_TRIES, tried ? 1u : 0u);
+            }
+        }
+    }
+}
+
 // SINGLE: a launch for one graph (mcm_match); the others (batches, the
 // server's multi-graph launch) compile the recorded-row Alternate out.
 template <bool WAVE, int S, bool SINGLE = true>
@@ -535,80 +620,8 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
     const uint32_t wpb = blockDim.x >> 6, blk = wave / wpb, nblk = nwaves / wpb;
     const bool dyn = (uint64_t)nwaves * B < n;
     uint32_t *ctr = s_tmp + kBatchCtr;
-    // expand one entry per lane (lanes with `have`)
     auto expand = [&](const int4 e, const bool have) {
-        int deg = 0;
-        uint32_t rdone = 0;
-        int cmate = -1;  // F_FASTALT: the entry column's mate (cmatch does not change during the BFS)
-        if (have) {
-            deg = e.w - e.z;
-            if (flags & F_FASTALT) cmate = g.cmatch[e.x];
-            if (late) rdone = ld_u<S>(&g.cdone[e.y]);
-            else if ((flags & F_WR) && deg > 0 && ld_u<S>(&g.cdone[e.y]) == ph) deg = 0;
-        }
-        if (flags & F_STATS) {
-            const bool live = !(late && rdone == ph);
-            acc.add(S_EDGES, live ? (uint64_t)deg : 0u);
-            acc.add(S_EXPANDED, (live && deg > 0) ? 1u : 0u);
-        }
-        if (WAVE) {
-            const int incl = wave_incl_scan(deg);
-            const int excl = incl - deg;
-            const int total = __shfl(incl, 63, 64);
-            for (int eb = 0; eb < total; eb += 64) {
-                const int k = eb + lane;
-                // owner lane: the largest o with excl[o] <= k (excl is non-decreasing)
-                int own = 0;
-#pragma unroll
-                for (int step = 32; step >= 1; step >>= 1) {
-                    const int v = __shfl(excl, own + step, 64);
-                    if (v <= k) own += step;
-                }
-                const int ocol = __shfl(e.x, own, 64);
-                const int oroot = __shfl(e.y, own, 64);
-                const int obeg = __shfl(e.z, own, 64);
-                const int oexcl = __shfl(excl, own, 64);
-                // (every lane takes part in the shuffles: a lane may read an
-                // owner that has no edge of its own in this round)
-                const int omate = (flags & F_FASTALT) ? __shfl(cmate, own, 64) : -1;
-                bool newcol = false, newend = false, tried = false;
-                int4 ne = make_int4(0, 0, 0, 0);
-                int r = 0;
-                if (k < total) {
-                    r = g.rowind[obeg + (k - oexcl)];
-                    const uint32_t odone = late ? (uint32_t)__shfl((int)rdone, own, 64) : 0u;
-                    if (!late || odone != ph)
-                        visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend, tried, omate);
-                }
-                push_entry(newcol, ne, o.split, st, io.next);
-                push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
-                any_end |= newend;
-                if (flags & F_STATS) {
-                    acc.add(S_CLAIMED, newcol ? 1u : 0u);
-                    acc.add(S_FOUND, newend ? 1u : 0u);
-                    acc.add(S_TRIES, tried ? 1u : 0u);
-                }
-            }
-        } else {
-            const int maxdeg = wave_max(deg);
-            for (int t = 0; t < maxdeg; ++t) {
-                bool newcol = false, newend = false, tried = false;
-                int4 ne = make_int4(0, 0, 0, 0);
-                int r = 0;
-                if (t < deg) {
-                    r = g.rowind[e.z + t];
-                    visit_edge<S>(g, e.x, e.y, r, ph, level, flags, newcol, ne, newend, tried, cmate);
-                }
-                push_entry(newcol, ne, o.split, st, io.next);
-                push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
-                any_end |= newend;
-                if (flags & F_STATS) {
-                    acc.add(S_CLAIMED, newcol ? 1u : 0u);
-                    acc.add(S_FOUND, newend ? 1u : 0u);
-                    acc.add(S_TRIES, tried ? 1u : 0u);
-                }
-            }
-        }
+        expand_entries<WAVE, S>(g, e, have, ph, level, flags, late, o, io, st, acc, any_end);
     };
     // one batch of entries [base, base + B) of the frontier
     auto batch = [&](const uint32_t base) {
@@ -654,15 +667,145 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
     return added;
 }
 
+// ---------------------------------------------------------------------
+// Level-free BFS of one APFB phase.  All frontier entries of the phase go
+// through one queue (fq0, 2 * qcap slots, each used at most once per
+// phase); wavefronts take entries as soon as they are written and expand
+// the columns they claim themselves (their LDS stage is their local work
+// list), so no grid barrier separates BFS levels.  A wavefront keeps at
+// most kKeep entries and hands older ones to the queue, where idle
+// wavefronts take them.  One 64-bit control word counts the entries
+// reserved in the queue (low half) and finished (high half): a wavefront
+// finishes the entries it took only once its stage is empty again (every
+// column they led to is expanded or handed on, and handing on reserves
+// first), so equal halves mean that no entry is held anywhere and none can
+// appear; the phase's BFS is then complete.  The trees stay alternating
+// trees (each row is still claimed once per phase, from a column of the
+// claimer's tree); they are no longer shortest-path trees, and the maximum
+// is still certified, because a phase that finds no unmatched row has
+// explored everything reachable from the unmatched columns.
+constexpr int kKeep = 128;
+
+// Hand the oldest entries of a wavefront's stage to the queue, keeping the
+// newest `keep` (wavefront-uniform call).
+DEV void drain_older(Stage &st, const QSink &k, int keep)
+{
+    const int n = st.nq - keep;
+    if (n <= 0) return;
+    wave_lds_sync();
+    uint32_t base = 0;
+    if (__lane_id() == 0)
+        base = (uint32_t)__hip_atomic_fetch_add(k.c64, (uint64_t)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    base = __shfl(base, 0, 64);
+    for (int i = __lane_id(); i < n; i += 64) put_entry(k, base + i, st.q[i]);
+    // move the kept entries to the front (they are the last `keep`, at most
+    // 64 lanes x 2 rounds)
+    int4 kept[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = __lane_id() + 64 * u;
+        kept[u] = i < keep ? st.q[n + i] : make_int4(0, 0, 0, 0);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = __lane_id() + 64 * u;
+        if (i < keep) st.q[i] = kept[u];
+    }
+    wave_lds_sync();
+    st.dq += n;
+    st.nq = keep;
+}
+
+template <bool WAVE>
+DEV void async_bfs(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t ph, uint32_t nwaves, Stage &st,
+                   Acc &acc)
+{
+    const int lane = __lane_id();
+    const uint32_t flags = o.flags;
+    const bool late = WAVE && (flags & F_WR) && (flags & F_WR_LATE);
+    uint64_t *aq = reinterpret_cast<uint64_t *>(line(ctrl, L_AQ));
+    uint32_t *take = line(ctrl, L_AQ_TAKE);
+    const QSink sink{g.fq0, nullptr, aq, true, 2 * g.qcap};
+    const LevelIO io{sink, line(ctrl, L_NENDS), nullptr, ctrl, false};
+    bool any_end = false;
+    uint32_t held = 0;
+    const uint64_t t0 = wall_clock64();
+    uint32_t naps = 0;
+    for (;;) {
+        if (st.nq > 0) {
+            // the newest (at most 64) of the entries this wavefront keeps
+            const int m = st.nq < 64 ? st.nq : 64;
+            wave_lds_sync();
+            const bool have = lane < m;
+            const int4 e = have ? st.q[st.nq - m + lane] : make_int4(0, 0, 0, 0);
+            wave_lds_sync();
+            st.nq -= m;
+            expand_entries<WAVE, kAgent>(g, e, have, ph, 0, flags, late, o, io, st, acc, any_end);
+            if (st.nq > kKeep) drain_older(st, sink, 64);
+            continue;
+        }
+        // stage empty: the entries taken are finished
+        if (held) {
+            if (lane == 0)
+                __hip_atomic_fetch_add(aq, (uint64_t)held << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            held = 0;
+        }
+        // take entries from the queue: slots [t, t + n), all reserved
+        uint32_t t = 0, n = 0;
+        int done = 0;
+        if (lane == 0) {
+            for (;;) {
+                const uint32_t tk = ld_u<kAgent>(take);
+                const uint64_t w = __hip_atomic_load(aq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t r = (uint32_t)w;
+                if (r > 2 * g.qcap) { set_status(ctrl, kEInternal); done = 1; break; }  // never: see put_entry
+                if (tk < r) {
+                    n = batch_size(r - tk, nwaves, o.batch_min);
+                    if (n > r - tk) n = r - tk;
+                    uint32_t expect = tk;
+                    if (__hip_atomic_compare_exchange_strong(take, &expect, tk + n, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        t = tk;
+                        naps = 0;
+                        break;
+                    }
+                    continue;
+                }
+                if ((uint32_t)(w >> 32) == r) { done = 1; break; }  // all reserved entries finished
+                if (status_of(ctrl) != 0) { done = 1; break; }
+                if (wall_clock64() - t0 > o.timeout) { set_status(ctrl, kEInternal); done = 1; break; }
+                // idle: back off (up to 64 s_sleep units)
+                for (uint32_t k = 0; k < (1u << (naps < 6 ? naps : 6)); ++k) __builtin_amdgcn_s_sleep(1);
+                ++naps;
+            }
+        }
+        if (__shfl(done, 0, 64)) break;
+        t = (uint32_t)__shfl((int)t, 0, 64);
+        n = (uint32_t)__shfl((int)n, 0, 64);
+        const bool have = (uint32_t)lane < n;
+        const int4 e = have ? take_entry(g.fq0, t + lane, ctrl, o.timeout) : make_int4(0, 0, 0, 0);
+        held = n;
+        expand_entries<WAVE, kAgent>(g, e, have, ph, 0, flags, late, o, io, st, acc, any_end);
+        if (st.nq > kKeep) drain_older(st, sink, 64);
+    }
+    // the unmatched rows this wavefront reached and still stages
+    if (st.ne) drain_ends(st, g.ends, io.ecnt, true);
+    st.dq = st.de = 0;
+    if ((flags & F_STATS) && threadIdx.x == 0) acc.tick(S_T_EXPAND, wall_clock64() - t0);
+}
+
 // InitBfsArray (paper, section 3, before Algorithm 2; root filled as in
 // Algorithm 4): every unmatched column with at least one edge becomes a
 // root and an entry of the first frontier.  Columns without edges can never
 // be matched and would expand nothing.  Every thread of the workgroup calls
 // it.
 DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const RunOpt &o, uint32_t *cnt, Stage &st,
-                    uint32_t *s_tmp, Acc &acc)
+                    uint32_t *s_tmp, Acc &acc, uint64_t *c64 = nullptr)
 {
-    const QSink q{g.fq0, cnt, nullptr, (o.flags & F_DEFER) != 0};
+    // the level-free BFS reserves root slots from its phase-long counter
+    const QSink q = c64 ? QSink{g.fq0, nullptr, c64, true, 2 * g.qcap}
+                        : QSink{g.fq0, cnt, nullptr, (o.flags & F_DEFER) != 0};
     const int lane = __lane_id();
     const uint32_t flags = o.flags;
     const uint32_t nc = (uint32_t)g.nc;
@@ -1137,6 +1280,18 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     for (;; ++ph) {
         if (ph > o.max_phases) { if (leader) set_status(ctrl, kEInternal); return false; }
         const uint32_t lv0 = total_levels;
+        if (SINGLE && (flags & F_ASYNC)) {
+            // level-free phase: roots reserved in the phase-long queue, one
+            // grid barrier, then every wavefront works until the queue's
+            // entries are all finished
+            init_roots(g, wave, nwaves, o, nullptr, st, s_tmp, acc, reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)));
+            if (timing && gr.b == 0) acc.tick(S_PASS, 4ull * (uint32_t)g.nc + (uint32_t)g.nc / 8);
+            if (!sync_all(none)) return false;
+            async_bfs<WAVE>(g, ctrl, o, ph, nwaves, st, acc);
+            ++total_levels;
+            if (!sync_all(none)) return false;
+            s = LvState{0, 0, 0};
+        } else {
         init_roots(g, wave, nwaves, o, fc(0), st, s_tmp, acc);
         if (timing && gr.b == 0) acc.tick(S_PASS, 4ull * (uint32_t)g.nc + (uint32_t)g.nc / 8);
         if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
@@ -1178,6 +1333,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
                       defer, [&](uint32_t base) { write_deferred(st, next, base, s_tmp); }))
                 return false;
         }
+        }
         // APsB stop: the frontier of level left.L (left.n entries) is never
         // expanded; with deferred writes its slots are set back to -1 once
         // they are certainly written (after the next grid barrier)
@@ -1200,6 +1356,8 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         if (leader) {
             for (int i = 0; i < 3; ++i) { *fc(i) = 0; *fd(i) = 0; }
             *line(ctrl, L_NENDS) = 0;
+            *reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)) = 0;
+            *line(ctrl, L_AQ_TAKE) = 0;
         }
         if (!sync_all(none)) return false;
         if (timing) acc.tick(S_T_AUGMENT, wall_clock64() - ta);
@@ -1275,7 +1433,7 @@ __global__ void k_setup(DevGraph g, const int32_t *init_c, const int32_t *init_r
             if (g.croot) g.croot[c] = -1;
         }
     }
-    if (flags & F_DEFER)
+    if (flags & (F_DEFER | F_ASYNC))
         for (uint64_t i = tid; i < 2 * g.qcap; i += nt) g.fq0[i] = make_int4(-1, -1, -1, -1);
     for (uint32_t r = tid; r < (uint32_t)g.nr; r += nt) {
         const int m = init_r ? init_r[r] : -1;

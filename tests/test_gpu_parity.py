@@ -27,11 +27,16 @@ DRIVER_COMBOS = [
     dict(driver="apfb", bfs="wr", mapping="wave", loop="device", endpoints="one"),
     dict(driver="apsb", bfs="wr", mapping="wave", loop="device", endpoints="all"),
     dict(driver="apsb", bfs="wr", mapping="thread", loop="host", endpoints="one"),
+    # level-free BFS (no grid barrier between levels)
+    dict(driver="apfb", bfs="wr", mapping="wave", loop="device", schedule="async"),
+    dict(driver="apfb", bfs="wr", mapping="thread", loop="device", schedule="async"),
+    dict(driver="apfb", bfs="plain", mapping="wave", loop="device", schedule="async"),
+    dict(driver="apfb", bfs="wr", mapping="wave", loop="device", endpoints="one", schedule="async"),
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
                 level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels=6,
-                alternate="auto")
+                alternate="auto", schedule="levels")
 
 
 @pytest.fixture(autouse=True)
@@ -202,6 +207,7 @@ def test_driver_variants(combo, name):
 # probe for R-MAT): drivers, mappings, both level loops, both end rules,
 # single-workgroup runs of small levels on and off, cheap and empty starts.
 CLAIM_COMBOS = [dict(driver="apfb", mapping="wave", loop="device", endpoints="auto", small_max=256),
+                dict(driver="apfb", mapping="wave", loop="device", endpoints="auto", schedule="async"),
                 dict(driver="apfb", mapping="thread", loop="device", endpoints="one", small_max=0),
                 dict(driver="apsb", mapping="wave", loop="device", endpoints="auto", small_max=0),
                 dict(driver="apsb", mapping="thread", loop="host", endpoints="all", small_max=256),
@@ -294,7 +300,10 @@ ALT_COMBOS = [dict(driver="apfb", mapping="wave", loop="device", endpoints="all"
               dict(driver="apfb", mapping="thread", loop="device", endpoints="all", local_levels=0),
               dict(driver="apsb", mapping="wave", loop="device", endpoints="one"),
               dict(driver="apfb", mapping="wave", loop="host", endpoints="all"),
-              dict(driver="apsb", mapping="thread", loop="host", endpoints="all")]
+              dict(driver="apsb", mapping="thread", loop="host", endpoints="all"),
+              dict(driver="apfb", bfs="plain", mapping="wave", loop="device", endpoints="all"),
+              dict(driver="apfb", mapping="wave", loop="device", endpoints="all", schedule="async"),
+              dict(driver="apfb", bfs="plain", mapping="thread", loop="device", endpoints="all", schedule="async")]
 
 
 @pytest.mark.parametrize("alt", ["fast", "classic"])
@@ -444,6 +453,11 @@ def test_batched_empty_members_and_no_init():
 
 
 # ------------------------------------------------------------------ full-size workloads (as timed by bench.py)
+import functools  # noqa: E402
+
+_full_workload = functools.lru_cache(maxsize=2)(gg.workload)  # generating rmat23 takes seconds
+
+
 def _full_size_card(g, name):
     """The oracle's |M| of a full-size workload, stored by
     tests/golden/make_full_size_cards.py, after checking that the stored
@@ -463,7 +477,7 @@ def test_full_size_certified(name):
     matching and the GPU's Konig cover (checked by the oracle's verifier)
     proves it maximum by weak duality; for the grid the size must also lie in
     the closed-form window n - |Rdel u Cdel| <= nu <= n - ndel."""
-    g = gg.workload(name)
+    g = _full_workload(name)
     ref = _full_size_card(g, name)
     card, cm, rm = _gpu(g)
     assert card == ref
@@ -476,14 +490,16 @@ def test_full_size_certified(name):
 
 @pytest.mark.parametrize("opts", [dict(claim="probe", flush="atomic", local_levels=0),
                                   dict(claim="max", flush="defer", local_levels=0),
-                                  dict(claim="probe", flush="defer", local_levels=16)],
+                                  dict(claim="probe", flush="defer", local_levels=16),
+                                  dict(schedule="async"),
+                                  dict(schedule="async", claim="probe", alternate="classic", wr_check="early")],
                          ids=lambda d: "-".join(str(v) for v in d.values()))
 @pytest.mark.parametrize("name", ["grid2048", "rmat23"])
 def test_full_size_other_forms(name, opts):
     """The full-size workloads with the claim, flush and local-level forms
     that the defaults do not pick for them: a valid matching certified
     maximum by the GPU's Konig cover, the same size as with the defaults."""
-    g = gg.workload(name)
+    g = _full_workload(name)
     ref = _full_size_card(g, name)
     _set(**opts)
     card, _, _ = _gpu(g)
