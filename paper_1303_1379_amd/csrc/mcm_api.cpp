@@ -93,7 +93,7 @@ static void release_workspace(Workspace &w)
     (void)hipSetDevice(w.device);
     (void)hipDeviceSynchronize();
     for (void *p : {(void *)w.rw, (void *)w.pred, (void *)w.cdone, (void *)w.fq, (void *)w.ends, (void *)w.radj,
-                    (void *)w.prow, (void *)w.cwork, (void *)w.ctrl, (void *)w.bar, (void *)w.desc, (void *)w.mctrl,
+                    (void *)w.prow, (void *)w.touched, (void *)w.rlist, (void *)w.cwork, (void *)w.ctrl, (void *)w.bar, (void *)w.desc, (void *)w.mctrl,
                     (void *)w.mbar, (void *)w.order, (void *)w.card, (void *)w.ptrace})
         free_dev(p);
     for (void *p : {(void *)w.h_ptrace, (void *)w.h_ctrl, (void *)w.h_desc, (void *)w.h_order, (void *)w.h_card})
@@ -194,6 +194,21 @@ static int64_t ensure_prow(Workspace &w, size_t nr)
         return fail(MCM_ENOMEM, "workspace allocation for %zu recorded rows failed", nr);
     }
     w.cap_prow = cap;
+    return 0;
+}
+
+// An int32 array of at least n elements, grown by half again when it must grow.
+static int64_t ensure_i32(int32_t *&p, size_t &cap, size_t n, const char *what)
+{
+    if (n <= cap) return 0;
+    free_dev(p);
+    p = nullptr;
+    const size_t c = std::max(n, cap + cap / 2);
+    if (hipMalloc(&p, sizeof(int32_t) * c) != hipSuccess) {
+        cap = 0;
+        return fail(MCM_ENOMEM, "workspace allocation of %zu %s failed", n, what);
+    }
+    cap = c;
     return 0;
 }
 
@@ -543,6 +558,8 @@ int64_t match_run(const RunBufs &b, const Options &o, uint32_t flags, bool singl
     g.ptrace = (flags & F_STATS) ? b.ptrace : nullptr;
     g.radj = (flags & F_MAXCLAIM) ? b.radj : nullptr;
     g.prow = (flags & F_FASTALT) ? b.prow : nullptr;
+    g.touched = o.fix != 0 ? b.touched : nullptr;
+    g.rlist = o.roots != 0 ? b.rlist : nullptr;
     g.qcap = b.cap_q;
     CoopHold hold(owner, st);  // at most one cooperative launch in flight in the process
     HIPCHK(launch_setup(g, init_cmatch, init_rmatch, b.ctrl, b.bar, flags, st));
@@ -571,6 +588,8 @@ RunBufs bufs_of(Workspace &w)
     b.ends = w.ends;
     b.radj = w.radj;
     b.prow = w.prow;
+    b.touched = w.touched;
+    b.rlist = w.rlist;
     b.ctrl = w.ctrl;
     b.bar = w.bar;
     b.ptrace = w.ptrace;
@@ -695,6 +714,16 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "defer") g_opt.flush = 1;
         else if (v == "auto") g_opt.flush = 2;
         else return (int)fail(MCM_EINVAL, "flush must be atomic, defer or auto");
+    } else if (k == "fix") {
+        if (v == "scan") g_opt.fix = 0;
+        else if (v == "list") g_opt.fix = 1;
+        else if (v == "auto") g_opt.fix = 2;
+        else return (int)fail(MCM_EINVAL, "fix must be scan, list or auto");
+    } else if (k == "roots") {
+        if (v == "scan") g_opt.roots = 0;
+        else if (v == "list") g_opt.roots = 1;
+        else if (v == "auto") g_opt.roots = 2;
+        else return (int)fail(MCM_EINVAL, "roots must be scan, list or auto");
     } else if (k == "schedule") {
         if (v == "levels") g_opt.schedule = 0;
         else if (v == "async") g_opt.schedule = 1;
@@ -766,6 +795,8 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "endpoints") v = o.endpoints == 0 ? "all" : (o.endpoints == 1 ? "one" : "auto");
     else if (k == "claim") v = o.claim == 0 ? "probe" : (o.claim == 1 ? "max" : "auto");
     else if (k == "schedule") v = o.schedule == 0 ? "levels" : (o.schedule == 1 ? "async" : "auto");
+    else if (k == "fix") v = o.fix == 0 ? "scan" : (o.fix == 1 ? "list" : "auto");
+    else if (k == "roots") v = o.roots == 0 ? "scan" : (o.roots == 1 ? "list" : "auto");
     else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
     else if (k == "local_levels") v = std::to_string(o.local_levels);
     else if (k == "alternate") v = o.alternate == 0 ? "classic" : (o.alternate == 1 ? "fast" : "auto");
@@ -859,6 +890,10 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     const uint32_t flags = match_flags(o, ncols, nrows, nnz, single_wg);
     if ((flags & F_MAXCLAIM) && (rc = ensure_radj(w, (size_t)nrows))) return rc;
     if ((flags & F_FASTALT) && (rc = ensure_prow(w, (size_t)nrows))) return rc;
+    if (!single_wg && o.fix != 0 && (rc = ensure_i32(w.touched, w.cap_touched, (size_t)nrows, "touched rows")))
+        return rc;
+    if (!single_wg && o.roots != 0 && (rc = ensure_i32(w.rlist, w.cap_rlist, 2 * (size_t)ncols, "listed roots")))
+        return rc;
     return match_run(bufs_of(w), o, flags, single_wg, ncols, nrows, colptr, rowind, init_cmatch, init_rmatch,
                      out_cmatch, out_rmatch, st, stream);
 }

@@ -92,6 +92,8 @@ struct Options {
     int local_levels = 6;     // grid levels: a wavefront expands its own new entries this many times more
     int alternate = 2;        // mcm_match's Alternate: 0 classic, 1 recorded rows, 2 auto (1 on low degree)
     int schedule = 0;         // mcm_match's BFS: 0 level-synchronous, 1 level-free, 2 auto
+    int fix = 2;              // mcm_match's FixMatching: 0 every row, 1 the rows the walks touched, 2 auto (1)
+    int roots = 2;            // mcm_match's root scan: 0 every column, 1 the previous phase's roots, 2 auto (1)
     int mapping = 2;          // 0 thread, 1 wave, 2 auto
     int loop = 2;             // 0 device, 1 host, 2 auto
     bool validate = false;
@@ -134,6 +136,10 @@ struct Workspace {
     size_t cap_radj = 0;
     int32_t *prow = nullptr;     // rows recorded by the claims (alternate=fast), grown on demand
     size_t cap_prow = 0;
+    int32_t *touched = nullptr;  // rows the walks of a phase touched (fix=list), grown on demand
+    size_t cap_touched = 0;
+    int32_t *rlist = nullptr;    // two halves of root lists (roots=list), grown on demand
+    size_t cap_rlist = 0;
     int32_t *cwork = nullptr;
     uint32_t *ctrl = nullptr;
     uint32_t *bar = nullptr;     // grid barrier arrival flags
@@ -165,6 +171,8 @@ struct RunBufs {
     int32_t *ends = nullptr;
     int2 *radj = nullptr;        // atomic-maximum claims only
     int32_t *prow = nullptr;     // recorded-row Alternate only
+    int32_t *touched = nullptr;  // [nr] FixMatching list, or null (every row)
+    int32_t *rlist = nullptr;    // [2 nc] root lists, or null (every column)
     uint32_t *ctrl = nullptr;    // control block [L_NLINES lines]
     uint32_t *bar = nullptr;     // [kMaxGridBlocks lines]
     uint32_t *ptrace = nullptr;  // [2 * kPhaseTrace] (stats runs), or null

@@ -29,6 +29,9 @@ enum CtrlLine : int {
     L_AQ,              // level-free BFS: entries reserved (low 32 bits) and finished (high 32) in the
                        // phase-long queue, one 64-bit word
     L_AQ_TAKE,         // level-free BFS: entries taken from that queue
+    L_NTOUCH,          // rows reported by the walks of this phase (length of DevGraph::touched)
+    L_NRL0,            // roots listed in DevGraph::rlist, even and odd phases
+    L_NRL1,
     L_STAT0,           // stats counters (64-bit each, own lines)
     L_NLINES = L_STAT0 + 14
 };
@@ -84,6 +87,10 @@ struct DevGraph {
     uint32_t *ptrace = nullptr;  // [2 * kPhaseTrace] per phase: BFS levels, unmatched rows reached
                                  // (recorded with F_STATS), or null
     int32_t *croot = nullptr;    // [nc]   F_LEVELS: root of the tree that reached each column, or null
+    int32_t *touched = nullptr;  // [nr]   rows the walks of a phase wrote or stopped at, for FixMatching to
+                                 //        visit instead of every row; null: FixMatching scans every row
+    int32_t *rlist = nullptr;    // [2 nc] the roots of the previous phase and of this one (halves by phase
+                                 //        parity), for the root scan to visit instead of every column; or null
 };
 
 // Options of one run, passed by value to the kernels.

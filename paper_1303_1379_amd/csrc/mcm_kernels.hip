@@ -170,24 +170,27 @@ DEV void put_end(int32_t *ge, uint32_t i, int32_t r, bool atomic)
 }
 
 // Hand a wavefront's staged ends to the global list now (its stage is full).
-DEV void drain_ends(Stage &st, int32_t *ge, uint32_t *gcnt, bool atomic)
+// `cap` (0: unchecked) bounds the list: entries past it are counted but not
+// stored, and the reader sees the count exceed the capacity.
+DEV void drain_ends(Stage &st, int32_t *ge, uint32_t *gcnt, bool atomic, uint32_t cap = 0)
 {
     wave_lds_sync();
     uint32_t base = 0;
     if (__lane_id() == 0) base = atomicAdd(gcnt, (uint32_t)st.ne);
     base = __shfl(base, 0, 64);
-    for (int i = __lane_id(); i < st.ne; i += 64) put_end(ge, base + i, st.e[i], atomic);
+    for (int i = __lane_id(); i < st.ne; i += 64)
+        if (!cap || base + (uint32_t)i < cap) put_end(ge, base + i, st.e[i], atomic);
     wave_lds_sync();
     st.de += st.ne;
     st.ne = 0;
 }
 
 // Append end r for every lane with p set (wavefront-uniform call).
-DEV void push_end(bool p, int32_t r, Stage &st, int32_t *ge, uint32_t *gcnt, bool atomic)
+DEV void push_end(bool p, int32_t r, Stage &st, int32_t *ge, uint32_t *gcnt, bool atomic, uint32_t cap = 0)
 {
     const uint64_t m = __ballot(p);
     if (m == 0) return;
-    if (st.ne > kStageE - 64) drain_ends(st, ge, gcnt, atomic);
+    if (st.ne > kStageE - 64) drain_ends(st, ge, gcnt, atomic, cap);
     if (p) st.e[st.ne + __popcll(m & lanemask_lt())] = r;
     st.ne += __popcll(m);
 }
@@ -372,10 +375,13 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
                 if (g.croot) g.croot[mate] = root;
             }
         } else {
-            st_i<S>(lo, -2);
             if ((flags & F_WR) && (flags & F_ENDPOINT)) {
+                // one end per root: a row reached after the first stays
+                // unmatched (-1); its stamp keeps it out of this phase
                 newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
+                st_i<S>(lo, newend ? -2 : -1);
             } else {
+                st_i<S>(lo, -2);
                 newend = true;
                 if (flags & F_WR) st_u<S>(&g.cdone[root], ph);
             }
@@ -408,8 +414,10 @@ DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, in
             if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
             if ((flags & F_WR) && (flags & F_ENDPOINT)) {
                 // the root's path ends at the first unmatched row it reached;
-                // a later one stays marked and FixMatching frees it
+                // a later one returns to unmatched (-1), its stamp keeping it
+                // out of this phase
                 newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
+                if (!newend) st_i<S>(reinterpret_cast<int32_t *>(g.rw) + 2 * (size_t)r, -1);
             } else {
                 newend = true;
                 if (flags & F_WR) st_u<S>(&g.cdone[root], ph);
@@ -799,9 +807,12 @@ DEV void async_bfs(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t 
 // Algorithm 4): every unmatched column with at least one edge becomes a
 // root and an entry of the first frontier.  Columns without edges can never
 // be matched and would expand nothing.  Every thread of the workgroup calls
-// it.
+// it.  With a root list (g.rlist), phase `ph` also lists its roots in half
+// ph & 1, and from the second phase on scans only the previous phase's
+// list: a matched column never becomes unmatched again, so the roots of a
+// phase are among those of the one before.
 DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const RunOpt &o, uint32_t *cnt, Stage &st,
-                    uint32_t *s_tmp, Acc &acc, uint64_t *c64 = nullptr)
+                    uint32_t *s_tmp, Acc &acc, uint64_t *c64 = nullptr, uint32_t ph = 1, uint32_t *ctrl = nullptr)
 {
     // the level-free BFS reserves root slots from its phase-long counter
     const QSink q = c64 ? QSink{g.fq0, nullptr, c64, true, 2 * g.qcap}
@@ -809,33 +820,45 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
     const int lane = __lane_id();
     const uint32_t flags = o.flags;
     const uint32_t nc = (uint32_t)g.nc;
+    const bool listed = g.rlist && ctrl;
+    int32_t *rl_out = listed ? g.rlist + (size_t)(ph & 1) * nc : nullptr;
+    uint32_t *rl_cnt = listed ? line(ctrl, (ph & 1) ? L_NRL1 : L_NRL0) : nullptr;
+    const int32_t *rl_in = listed && ph > 1 ? g.rlist + (size_t)((ph - 1) & 1) * nc : nullptr;
+    // the columns to scan: all, or the previous phase's roots
+    const uint32_t n = rl_in ? ld_u<kAgent>(line(ctrl, ((ph - 1) & 1) ? L_NRL1 : L_NRL0)) : nc;
     // kStream chunks of 64 columns per wavefront and step, their loads
     // issued together (indices clamped, so every load is in bounds and
     // unconditional; a clamped lane is masked afterwards)
-    for (uint32_t base = wave * 64u * kStream; base < nc; base += nwaves * 64u * kStream) {
-        int cm[kStream], b[kStream], en[kStream];
+    for (uint32_t base = wave * 64u * kStream; base < n; base += nwaves * 64u * kStream) {
+        int col[kStream], cm[kStream], b[kStream], en[kStream];
 #pragma unroll
         for (int u = 0; u < kStream; ++u) {
-            const uint32_t c = min(base + 64u * u + (uint32_t)lane, nc - 1);
-            cm[u] = g.cmatch[c];
-            b[u] = g.colptr[c];
-            en[u] = g.colptr[c + 1];
+            const uint32_t i = min(base + 64u * u + (uint32_t)lane, n - 1);
+            col[u] = rl_in ? rl_in[i] : (int)i;
         }
 #pragma unroll
         for (int u = 0; u < kStream; ++u) {
-            const uint32_t c = base + 64u * u + (uint32_t)lane;
-            const bool in = c < nc, un = in && cm[u] == -1;
+            cm[u] = g.cmatch[col[u]];
+            b[u] = g.colptr[col[u]];
+            en[u] = g.colptr[col[u] + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) {
+            const int c = col[u];
+            const bool in = base + 64u * u + (uint32_t)lane < n, un = in && cm[u] == -1;
             const bool p = un && en[u] > b[u];
-            const int4 e = make_int4((int)c, (int)c, b[u], en[u]);
+            const int4 e = make_int4(c, c, b[u], en[u]);
             if ((flags & F_LEVELS) && in) {
                 g.clevel[c] = un ? 0 : -1;
-                if (g.croot) g.croot[c] = un ? (int)c : -1;
+                if (g.croot) g.croot[c] = un ? c : -1;
             }
             if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
             push_entry(p, e, o.split, st, q);
+            if (listed) push_end(p, c, st, rl_out, rl_cnt, q.atomic);
         }
     }
-    block_flush(st, q, g.ends, nullptr, s_tmp, false);
+    if ((flags & F_STATS) && threadIdx.x == 0 && wave == 0) acc.tick(S_PASS, 4ull * n + nc / 8);
+    block_flush(st, q, listed ? rl_out : g.ends, rl_cnt, s_tmp, false);
 }
 
 // Alternate (Algorithm 3) from every reached unmatched row, one thread per
@@ -896,6 +919,88 @@ DEV void alternate(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nth
         }
     }
     if (flags & F_STATS) acc.add(S_ALT, steps);
+}
+
+// Alternate as above, every walk also reporting each row it wrote, and the
+// row a classic walk stops at (whose column it leaves pointing elsewhere),
+// to the phase's list g.touched (counted in *tcnt), so that FixMatching
+// visits only those rows.  Each lane walks one end at a time and takes its
+// next end when its walk is done; the loop runs while any lane of the
+// wavefront walks, and reports are compacted per wavefront in LDS (the
+// stage of ends, empty after the BFS).  Wavefront-uniform call.
+template <int S>
+DEV void alternate_listed(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nthreads, uint32_t flags,
+                          uint32_t *ctrl, Acc &acc, Stage &st, uint32_t *tcnt)
+{
+    uint64_t steps = 0;
+    int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);
+    const bool fast = (flags & F_FASTALT) != 0;
+    uint32_t i = tid, guard = 0;
+    bool active = i < nends;
+    int r = 0, c = 0;
+    if (active) {
+        r = g.ends[i];
+        if (!fast) c = ld_i<S>(&g.pred[r]);
+    }
+    while (__ballot(active)) {
+        int touched = -1;
+        if (active) {
+            bool done = false;
+            if (fast) {
+                const int cc = ld_i<S>(&g.pred[r]);
+                const int r2 = ld_i<S>(&g.prow[r]);
+                st_i<S>(&g.cmatch[cc], r);
+                st_i<S>(&rlo[2 * (size_t)r], cc);
+                if (flags & F_MAXCLAIM) g.radj[r] = make_int2(g.colptr[cc], g.colptr[cc + 1]);
+                ++steps;
+                touched = r;
+                if (r2 == -1) done = true;
+                else r = r2;
+            } else {
+                const int r2 = ld_i<S>(&g.cmatch[c]);
+                const int c2 = r2 != -1 ? ld_i<S>(&g.pred[r2]) : -1;
+                touched = r;
+                if (r2 != -1 && c2 == c) {
+                    done = true;  // c already flipped by another walk; r keeps its old column
+                } else {
+                    st_i<S>(&g.cmatch[c], r);
+                    st_i<S>(&rlo[2 * (size_t)r], c);
+                    if (flags & F_MAXCLAIM) g.radj[r] = make_int2(g.colptr[c], g.colptr[c + 1]);
+                    ++steps;
+                    if (r2 == -1) done = true;
+                    else { r = r2; c = c2; }
+                }
+            }
+            if (!done && ++guard > (uint32_t)g.nc + 1u) { set_status(ctrl, kEInternal); done = true; }
+            if (done) {
+                i += nthreads;
+                guard = 0;
+                active = i < nends;
+                if (active) {
+                    r = g.ends[i];
+                    if (!fast) c = ld_i<S>(&g.pred[r]);
+                }
+            }
+        }
+        push_end(touched >= 0, touched, st, g.touched, tcnt, true, (uint32_t)g.nr);
+    }
+    if (st.ne) drain_ends(st, g.touched, tcnt, true, (uint32_t)g.nr);
+    if (flags & F_STATS) acc.add(S_ALT, steps);
+}
+
+// FixMatching over the rows the walks reported (duplicates are harmless:
+// the rule only ever writes -1): the same rule as fix_matching.
+DEV void fix_listed(const DevGraph &g, uint32_t n, uint32_t tid, uint32_t nthreads, uint32_t flags, Acc &acc)
+{
+    uint64_t resets = 0;
+    int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);
+    for (uint32_t i = tid; i < n; i += nthreads) {
+        const int r = g.touched[i];
+        const int m = rlo[2 * (size_t)r];
+        if (m == -1) continue;
+        if (m < 0 || g.cmatch[m] != r) { rlo[2 * (size_t)r] = -1; resets += (m >= 0); }
+    }
+    if (flags & F_STATS) acc.add(S_FIX, resets);
 }
 
 // FixMatching: a row whose column points elsewhere lost a race and is
@@ -1279,21 +1384,23 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     const Pub none{0, 0, 0, nullptr, nullptr, false};
     for (;; ++ph) {
         if (ph > o.max_phases) { if (leader) set_status(ctrl, kEInternal); return false; }
+        // every block read the previous phase's count before that phase's
+        // last grid barrier; the walks of this phase report after two more
+        if (leader) *line(ctrl, L_NTOUCH) = 0;
         const uint32_t lv0 = total_levels;
         if (SINGLE && (flags & F_ASYNC)) {
             // level-free phase: roots reserved in the phase-long queue, one
             // grid barrier, then every wavefront works until the queue's
             // entries are all finished
-            init_roots(g, wave, nwaves, o, nullptr, st, s_tmp, acc, reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)));
-            if (timing && gr.b == 0) acc.tick(S_PASS, 4ull * (uint32_t)g.nc + (uint32_t)g.nc / 8);
+            init_roots(g, wave, nwaves, o, nullptr, st, s_tmp, acc, reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)), ph,
+                       ctrl);
             if (!sync_all(none)) return false;
             async_bfs<WAVE>(g, ctrl, o, ph, nwaves, st, acc);
             ++total_levels;
             if (!sync_all(none)) return false;
             s = LvState{0, 0, 0};
         } else {
-        init_roots(g, wave, nwaves, o, fc(0), st, s_tmp, acc);
-        if (timing && gr.b == 0) acc.tick(S_PASS, 4ull * (uint32_t)g.nc + (uint32_t)g.nc / 8);
+        init_roots(g, wave, nwaves, o, fc(0), st, s_tmp, acc, nullptr, ph, ctrl);
         if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
         for (;;) {
             const int L = (int)s.L;
@@ -1345,10 +1452,21 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         }
         if (ne == 0 || (flags & F_NOAUG)) break;
         const uint64_t ta = timing ? wall_clock64() : 0;
-        alternate<kAgent>(g, ne, tid, nthreads, SINGLE ? flags : (flags & ~(uint32_t)F_FASTALT), ctrl, acc);
+        if (SINGLE && g.touched)
+            alternate_listed<kAgent>(g, ne, tid, nthreads, flags, ctrl, acc, st, line(ctrl, L_NTOUCH));
+        else
+            alternate<kAgent>(g, ne, tid, nthreads, SINGLE ? flags : (flags & ~(uint32_t)F_FASTALT), ctrl, acc);
         if (!sync_all(none)) return false;
-        fix_matching(g, tid, nthreads, flags, acc);
-        if (timing && gr.b == 0) acc.tick(S_PASS, 8ull * (uint32_t)g.nr);
+        // FixMatching over the rows the walks touched, unless more were
+        // reported than the list holds (then over every row)
+        const uint32_t ntouch = (SINGLE && g.touched) ? ld_u<kAgent>(line(ctrl, L_NTOUCH)) : 0xffffffffu;
+        if (ntouch <= (uint32_t)g.nr) {
+            fix_listed(g, ntouch, tid, nthreads, flags, acc);
+            if (timing && gr.b == 0) acc.tick(S_PASS, 8ull * ntouch);
+        } else {
+            fix_matching(g, tid, nthreads, flags, acc);
+            if (timing && gr.b == 0) acc.tick(S_PASS, 8ull * (uint32_t)g.nr);
+        }
         if ((flags & F_DEFER) && left.stop) {
             const QSink lq{(left.L & 1) ? g.fq1 : g.fq0, nullptr, nullptr, true};
             for (uint32_t i = tid; i < left.n; i += nthreads) put_entry(lq, i, make_int4(-1, -1, -1, -1));
@@ -1358,6 +1476,8 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             *line(ctrl, L_NENDS) = 0;
             *reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)) = 0;
             *line(ctrl, L_AQ_TAKE) = 0;
+            // the next phase lists its roots in the half this phase read
+            *line(ctrl, ((ph + 1) & 1) ? L_NRL1 : L_NRL0) = 0;
         }
         if (!sync_all(none)) return false;
         if (timing) acc.tick(S_T_AUGMENT, wall_clock64() - ta);
@@ -1381,7 +1501,6 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, Acc &acc,
         if (threadIdx.x == 0) for (int i = 0; i < 5; ++i) s_loc[i] = 0;
         __syncthreads();
         init_roots(g, wave, nwaves, o, &s_loc[0], st, s_tmp, acc);
-        if (flags & F_STATS) acc.tick(S_PASS, 4ull * (uint32_t)g.nc + (uint32_t)g.nc / 8);
         int L = 0;
         for (;;) {
             const uint32_t n = *(volatile uint32_t *)&s_loc[L % 3];
@@ -1645,7 +1764,6 @@ __global__ void k_init_roots(DevGraph g, uint32_t *ctrl, RunOpt o)
     __shared__ uint64_t s_acc[kAccN];
     Acc acc = make_acc(s_acc);
     init_roots(g, wave, nwaves, o, line(ctrl, L_FCOUNT0), st, stage_tmp(smem), acc);
-    if ((flags & F_STATS) && blockIdx.x == 0) acc.tick(S_PASS, 4ull * (uint32_t)g.nc + (uint32_t)g.nc / 8);
     if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
 }
 

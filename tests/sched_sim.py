@@ -88,12 +88,15 @@ def bfs_phase(colptr, rowind, cmatch, rmatch, rng: random.Random, wr=True, order
             root[m] = R
             push(m)
         else:
-            marked[r] = True
             if one_end:
+                # one end per root: a row reached after the first is left
+                # unmatched at once (its claim keeps it out of the phase)
                 if not done[R]:
                     ends.append(r)
+                    marked[r] = True
             else:
                 ends.append(r)
+                marked[r] = True
             if wr:
                 done[R] = True
 
@@ -134,8 +137,9 @@ def bfs_phase(colptr, rowind, cmatch, rmatch, rng: random.Random, wr=True, order
     return Forest(pred, prow, root, ends, marked)
 
 
-def _walk_classic(f: Forest, cmatch, rmatch, e):
-    """Algorithm 3 from end e, one memory access per yield."""
+def _walk_classic(f: Forest, cmatch, rmatch, e, touched):
+    """Algorithm 3 from end e, one memory access per yield; every row it
+    writes, and the row it stops at, is reported to `touched`."""
     r = e
     c = f.pred[r]
     yield
@@ -147,17 +151,19 @@ def _walk_classic(f: Forest, cmatch, rmatch, e):
             c2 = f.pred[r2]
             yield
             if c2 == c:
+                touched.append(r)             # r keeps its old column
                 return                        # c was already flipped by another walk
         cmatch[c] = r
         yield
         rmatch[r] = c
+        touched.append(r)
         yield
         if r2 == -1:
             return                            # reached the root
         r, c = r2, c2
 
 
-def _walk_recorded(f: Forest, cmatch, rmatch, e):
+def _walk_recorded(f: Forest, cmatch, rmatch, e, touched):
     """The recorded-row walk from end e: pred and the recorded row, no check."""
     r = e
     while True:
@@ -168,6 +174,7 @@ def _walk_recorded(f: Forest, cmatch, rmatch, e):
         cmatch[c] = r
         yield
         rmatch[r] = c
+        touched.append(r)
         yield
         if r2 == -1:
             return
@@ -180,13 +187,14 @@ def alternate(f: Forest, cmatch, rmatch, rng: random.Random, walk="recorded", sc
     access each, as lanes of a wavefront) or "sequential" (one walk after
     the other, in a random order)."""
     mk = _walk_recorded if walk == "recorded" else _walk_classic
-    walks = [mk(f, cmatch, rmatch, e) for e in f.ends]
+    touched = []
+    walks = [mk(f, cmatch, rmatch, e, touched) for e in f.ends]
     if schedule == "sequential":
         rng.shuffle(walks)
         for w in walks:
             for _ in w:
                 pass
-        return
+        return touched
     live = list(walks)
     while live:
         if schedule == "lockstep":
@@ -204,13 +212,15 @@ def alternate(f: Forest, cmatch, rmatch, rng: random.Random, walk="recorded", sc
                 next(live[i])
             except StopIteration:
                 live.pop(i)
+    return touched
 
 
-def fix_matching(cmatch, rmatch, marked):
+def fix_matching(cmatch, rmatch, marked, rows=None):
     """Rows still marked -2 and rows whose column points elsewhere become
-    unmatched; cmatch is not touched."""
-    for r in range(len(rmatch)):
-        if marked[r] and rmatch[r] < 0:
+    unmatched; cmatch is not touched.  `rows`: only these rows (the rows
+    the walks reported), else every row."""
+    for r in (range(len(rmatch)) if rows is None else rows):
+        if rmatch[r] < -1:
             rmatch[r] = -1
         elif rmatch[r] >= 0 and cmatch[rmatch[r]] != r:
             rmatch[r] = -1
@@ -223,7 +233,7 @@ def phase(colptr, rowind, cmatch, rmatch, rng, **kw):
     # rows reached as ends carry -2 until Alternate or FixMatching settles them
     for r in np.flatnonzero(f.marked):
         rmatch[r] = -2
-    alternate(f, cmatch, rmatch, rng, walk=kw.get("walk", "recorded"), schedule=kw.get("schedule", "random"))
-    fix_matching(cmatch, rmatch, f.marked)
+    touched = alternate(f, cmatch, rmatch, rng, walk=kw.get("walk", "recorded"), schedule=kw.get("schedule", "random"))
+    fix_matching(cmatch, rmatch, f.marked, touched if kw.get("fix", "scan") == "list" else None)
     trees = len({int(f.root[f.pred[e]]) for e in f.ends})
     return f, trees

@@ -36,7 +36,7 @@ DRIVER_COMBOS = [
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
                 level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels=6,
-                alternate="auto", schedule="levels")
+                alternate="auto", schedule="levels", fix="auto", roots="auto")
 
 
 @pytest.fixture(autouse=True)
@@ -314,6 +314,25 @@ def test_alternate_forms(alt, combo, name):
     _set(wg_threshold=0, alternate=alt, **combo)
     assert _gpu(g)[0] == _oracle_card(g), (alt, combo)
     assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (alt, combo)
+
+
+# FixMatching over every row or over the rows the walks reported, the root
+# scan over every column or over the previous phase's roots, with both
+# schedules and both walks; one end per root leaves the other unmatched rows
+# it reaches unmatched at once (no row is left marked for FixMatching).
+@pytest.mark.parametrize("fix", ["scan", "list"])
+@pytest.mark.parametrize("roots", ["scan", "list"])
+@pytest.mark.parametrize("form", [dict(schedule="levels", alternate="fast"), dict(schedule="levels", alternate="classic"),
+                                  dict(schedule="async", alternate="fast"), dict(schedule="async", alternate="classic"),
+                                  dict(schedule="levels", alternate="classic", endpoints="one"),
+                                  dict(schedule="async", alternate="fast", endpoints="one", bfs="wr")],
+                         ids=lambda d: "-".join(str(v) for v in d.values()))
+@pytest.mark.parametrize("name", ["grid128", "rmat13", "grid256p"])
+def test_listed_passes(fix, roots, form, name):
+    g = gg.workload(name)
+    _set(wg_threshold=0, fix=fix, roots=roots, **form)
+    assert _gpu(g)[0] == _oracle_card(g), (fix, roots, form)
+    assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (fix, roots, form)
 
 
 def test_deferred_levels_repeated():

@@ -12,6 +12,8 @@ After every phase, whatever the schedule:
       recorded-row walk that has none, with several ends per tree sharing
       their way to the root;
   I4  no row is left marked -2.
+FixMatching runs over every row, or only over the rows the walks report
+(each row a walk writes, and the row a classic walk stops at).
 Phases repeat until a BFS finds no end; the result then equals the
 oracle's maximum.  A planted mistake in FixMatching must break I1 or I4."""
 import random
@@ -59,10 +61,11 @@ def _run(g, init, rng, **kw):
         assert phases <= g.nc + 1
 
 
-KW = [dict(walk=w, schedule=s, order=o, wr=wr, one_end=oe, local_p=lp)
+KW = [dict(walk=w, schedule=s, order=o, wr=wr, one_end=oe, local_p=lp, fix=fx)
       for w in ("recorded", "classic") for s in ("random", "lockstep", "sequential")
       for o, lp in (("levels", 0.0), ("levels", 0.5), ("lockstep", 0.0), ("pool", 0.0))
-      for wr, oe in ((True, False), (True, True), (False, False))]
+      for wr, oe in ((True, False), (True, True), (False, False))
+      for fx in ("scan", "list")]
 
 
 @pytest.mark.parametrize("kw", KW, ids=lambda d: "-".join(f"{k}={v}" for k, v in d.items()))
@@ -102,9 +105,9 @@ def test_planted_fix_mistake_is_caught():
     schedule of the recorded-row walk."""
     real = S.fix_matching
 
-    def broken(cmatch, rmatch, marked):
+    def broken(cmatch, rmatch, marked, rows=None):
         for r in range(len(rmatch)):
-            if marked[r] and rmatch[r] < 0:
+            if rmatch[r] < -1:
                 rmatch[r] = -1
 
     S.fix_matching = broken
@@ -123,3 +126,37 @@ def test_planted_fix_mistake_is_caught():
         assert caught
     finally:
         S.fix_matching = real
+
+
+def test_listed_fix_needs_the_stop_rows():
+    """With FixMatching over the reported rows only, a classic walk that does
+    not report the row it stops at leaves that row pointing at a column
+    that took another row: I1 must fail on some schedule."""
+    real = S._walk_classic
+
+    def no_stop_report(f, cmatch, rmatch, e, touched):
+        sink = []
+        for x in real(f, cmatch, rmatch, e, sink):
+            yield x
+        # report every row but a stop row: the last reported one if it was
+        # not written by this walk (its column points elsewhere)
+        for r in sink:
+            if rmatch[r] >= 0 and cmatch[rmatch[r]] == r or r != sink[-1]:
+                touched.append(r)
+
+    S._walk_classic = no_stop_report
+    try:
+        caught = False
+        rng = random.Random(9)
+        for g in _graphs():
+            for _ in range(4):
+                try:
+                    _run(g, "cheap", rng, walk="classic", schedule="random", wr=False, fix="list")
+                except AssertionError:
+                    caught = True
+                    break
+            if caught:
+                break
+        assert caught
+    finally:
+        S._walk_classic = real
