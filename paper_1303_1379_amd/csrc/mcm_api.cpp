@@ -266,6 +266,8 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     r.level_entries = (uint32_t)o.level_entries;
     r.idle_sleep = (uint32_t)o.idle_sleep;
     r.local_levels = (uint32_t)o.local_levels;
+    r.take = (uint32_t)std::min(o.take, 64);
+    r.keep = (uint32_t)std::max(o.keep, o.take);
     r.timeout = (uint64_t)(o.timeout_s * info.clock_khz * 1000.0);
     return r;
 }
@@ -714,6 +716,12 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "defer") g_opt.flush = 1;
         else if (v == "auto") g_opt.flush = 2;
         else return (int)fail(MCM_EINVAL, "flush must be atomic, defer or auto");
+    } else if (k == "keep") {
+        if (!as_int(1, 192, &x)) return (int)fail(MCM_EINVAL, "keep must be in [1, 192]");
+        g_opt.keep = (int)x;
+    } else if (k == "take") {
+        if (!as_int(1, 64, &x)) return (int)fail(MCM_EINVAL, "take must be in [1, 64]");
+        g_opt.take = (int)x;
     } else if (k == "fix") {
         if (v == "scan") g_opt.fix = 0;
         else if (v == "list") g_opt.fix = 1;
@@ -796,6 +804,8 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "claim") v = o.claim == 0 ? "probe" : (o.claim == 1 ? "max" : "auto");
     else if (k == "schedule") v = o.schedule == 0 ? "levels" : (o.schedule == 1 ? "async" : "auto");
     else if (k == "fix") v = o.fix == 0 ? "scan" : (o.fix == 1 ? "list" : "auto");
+    else if (k == "keep") v = std::to_string(o.keep);
+    else if (k == "take") v = std::to_string(o.take);
     else if (k == "roots") v = o.roots == 0 ? "scan" : (o.roots == 1 ? "list" : "auto");
     else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
     else if (k == "local_levels") v = std::to_string(o.local_levels);

@@ -681,7 +681,7 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
 // phase); wavefronts take entries as soon as they are written and expand
 // the columns they claim themselves (their LDS stage is their local work
 // list), so no grid barrier separates BFS levels.  A wavefront keeps at
-// most kKeep entries and hands older ones to the queue, where idle
+// at most o.keep entries and hands older ones to the queue, where idle
 // wavefronts take them.  One 64-bit control word counts the entries
 // reserved in the queue (low half) and finished (high half): a wavefront
 // finishes the entries it took only once its stage is empty again (every
@@ -692,8 +692,6 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
 // claimer's tree); they are no longer shortest-path trees, and the maximum
 // is still certified, because a phase that finds no unmatched row has
 // explored everything reachable from the unmatched columns.
-constexpr int kKeep = 128;
-
 // Hand the oldest entries of a wavefront's stage to the queue, keeping the
 // newest `keep` (wavefront-uniform call).
 DEV void drain_older(Stage &st, const QSink &k, int keep)
@@ -742,15 +740,15 @@ DEV void async_bfs(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t 
     uint32_t naps = 0;
     for (;;) {
         if (st.nq > 0) {
-            // the newest (at most 64) of the entries this wavefront keeps
-            const int m = st.nq < 64 ? st.nq : 64;
+            // the newest (at most o.take) of the entries this wavefront keeps
+            const int m = st.nq < (int)o.take ? st.nq : (int)o.take;
             wave_lds_sync();
             const bool have = lane < m;
             const int4 e = have ? st.q[st.nq - m + lane] : make_int4(0, 0, 0, 0);
             wave_lds_sync();
             st.nq -= m;
             expand_entries<WAVE, kAgent>(g, e, have, ph, 0, flags, late, o, io, st, acc, any_end);
-            if (st.nq > kKeep) drain_older(st, sink, 64);
+            if (st.nq > (int)o.keep) drain_older(st, sink, (int)o.take);
             continue;
         }
         // stage empty: the entries taken are finished
@@ -795,7 +793,7 @@ DEV void async_bfs(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t 
         const int4 e = have ? take_entry(g.fq0, t + lane, ctrl, o.timeout) : make_int4(0, 0, 0, 0);
         held = n;
         expand_entries<WAVE, kAgent>(g, e, have, ph, 0, flags, late, o, io, st, acc, any_end);
-        if (st.nq > kKeep) drain_older(st, sink, 64);
+        if (st.nq > (int)o.keep) drain_older(st, sink, (int)o.take);
     }
     // the unmatched rows this wavefront reached and still stages
     if (st.ne) drain_ends(st, g.ends, io.ecnt, true);
