@@ -38,8 +38,11 @@
  *   - Errors: a negative return value is an mcm_status; mcm_strerror()
  *     gives the message of the calling thread's last error.  No C++
  *     exception crosses this interface.
- *   - Concurrency: entry points may be called from several host threads;
- *     calls that share the library workspace are serialised internally.
+ *   - Concurrency: entry points may be called from several host threads.
+ *     Calls on the same stream share one library workspace and are
+ *     serialised; calls on different streams use separate workspaces (each
+ *     grows to the largest graph it has served, until mcm_shutdown) and may
+ *     run at the same time.
  *     The library keeps at most one cooperative (whole-device) launch in
  *     flight in the process: mcm_match, mcm_konig_cover and mcm_bfs_levels
  *     on graphs above the one-workgroup size, the multi-graph launches of

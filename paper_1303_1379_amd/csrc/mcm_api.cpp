@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <numeric>
 #include <vector>
 
@@ -72,11 +73,27 @@ Options opts()
 }
 
 // ------------------------------------------------------------------ workspace
-std::mutex g_ws_mu;
-Workspace g_ws[64];
+// One workspace per (device, stream), each with its own lock.  Slots live
+// until mcm_shutdown (map nodes do not move).
+struct WsSlot {
+    std::mutex mu;
+    Workspace w;
+};
+std::mutex g_ws_map_mu;
+std::map<std::pair<int, const void *>, std::unique_ptr<WsSlot>> g_ws_map;
 
-Workspace &workspace(int dev) { return g_ws[dev]; }
-std::mutex &workspace_mutex() { return g_ws_mu; }
+Workspace &acquire_workspace(int dev, const void *stream, std::unique_lock<std::mutex> &lk)
+{
+    WsSlot *slot;
+    {
+        std::lock_guard<std::mutex> g(g_ws_map_mu);
+        std::unique_ptr<WsSlot> &p = g_ws_map[{dev, stream}];
+        if (!p) p.reset(new WsSlot());
+        slot = p.get();
+    }
+    lk = std::unique_lock<std::mutex>(slot->mu);
+    return slot->w;
+}
 mcm_stats g_stats;
 std::mutex g_stats_mu;
 std::vector<uint32_t> g_phases;  // per-phase (levels, ends) of the last stats run of mcm_match
@@ -884,8 +901,8 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     int dev = 0;
     if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
     const Options o = opts();
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace &w = g_ws[dev];
+    std::unique_lock<std::mutex> lk;
+    Workspace &w = acquire_workspace(dev, stream, lk);
     if ((rc = ensure_base(w, dev))) return rc;
     const bool single_wg = (int64_t)ncols + nrows <= o.wg_threshold;
     size_t qcap = 0;
@@ -982,8 +999,8 @@ int64_t mcm_konig_cover(int32_t ncols, int32_t nrows, const int32_t *colptr, con
     int dev = 0;
     if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
     const Options o = opts();
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace &w = g_ws[dev];
+    std::unique_lock<std::mutex> lk;
+    Workspace &w = acquire_workspace(dev, stream, lk);
     if ((rc = ensure_base(w, dev))) return rc;
     CoopHold hold(stream, st);
     DevGraph g;
@@ -1015,8 +1032,8 @@ int64_t mcm_bfs_levels(int32_t ncols, int32_t nrows, const int32_t *colptr, cons
     int dev = 0;
     if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
     const Options o = opts();
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace &w = g_ws[dev];
+    std::unique_lock<std::mutex> lk;
+    Workspace &w = acquire_workspace(dev, stream, lk);
     if ((rc = ensure_base(w, dev))) return rc;
     CoopHold hold(stream, st);
     DevGraph g;
@@ -1052,8 +1069,8 @@ int64_t mcm_bfs_forest(int32_t ncols, int32_t nrows, const int32_t *colptr, cons
     int dev = 0;
     if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
     const Options o = opts();
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace &w = g_ws[dev];
+    std::unique_lock<std::mutex> lk;
+    Workspace &w = acquire_workspace(dev, stream, lk);
     if ((rc = ensure_base(w, dev))) return rc;
     CoopHold hold(stream, st);
     DevGraph g;
@@ -1078,8 +1095,12 @@ int mcm_shutdown(void)
     int dev = 0;
     const bool have_dev = current_device(&dev) == 0;
     {
-        std::lock_guard<std::mutex> lk(g_ws_mu);
-        for (auto &w : g_ws) release_workspace(w);
+        std::lock_guard<std::mutex> g(g_ws_map_mu);
+        for (auto &kv : g_ws_map) {
+            std::lock_guard<std::mutex> lk(kv.second->mu);
+            release_workspace(kv.second->w);
+        }
+        g_ws_map.clear();
     }
     if (have_dev) (void)hipSetDevice(dev);
     return MCM_OK;

@@ -196,8 +196,8 @@ int64_t mcm_match_batched(int32_t ngraphs, const mcm_graph *graphs, const int32_
     int dev = 0;
     if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
     const Options o = opts();
-    std::lock_guard<std::mutex> lk(workspace_mutex());
-    Workspace &w = workspace(dev);
+    std::unique_lock<std::mutex> lk;
+    Workspace &w = acquire_workspace(dev, stream, lk);
     if ((rc = ensure_base(w, dev))) return rc;
     const size_t ce = (size_t)std::max<int64_t>(ex.col_ext, 1), re = (size_t)std::max<int64_t>(ex.row_ext, 1);
     if ((rc = ensure_graph(w, ce, re, ce))) return rc;  // queues: 2 * col_ext entries in all
@@ -437,8 +437,8 @@ int64_t mcm_batch_plan_create(int32_t ngraphs, const mcm_graph *graphs, const in
     auto bail = [&](int64_t code) { plan_free(p); return code; };
     DevInfo info;
     {
-        std::lock_guard<std::mutex> lk(workspace_mutex());
-        Workspace &w = workspace(dev);
+        std::unique_lock<std::mutex> lk;
+        Workspace &w = acquire_workspace(dev, nullptr, lk);
         if ((rc = ensure_base(w, dev))) return bail(rc);
         info = w.info;
     }
@@ -554,8 +554,8 @@ int64_t mcm_cheap_init(int32_t ncols, int32_t nrows, const int32_t *colptr, cons
     }
     int dev = 0;
     if (current_device(&dev) || dev < 0 || dev >= 64) return fail(MCM_EHIP, "no current HIP device");
-    std::lock_guard<std::mutex> lk(workspace_mutex());
-    Workspace &w = workspace(dev);
+    std::unique_lock<std::mutex> lk;
+    Workspace &w = acquire_workspace(dev, stream, lk);
     int64_t rc;
     if ((rc = ensure_base(w, dev))) return rc;
     if ((rc = ensure_desc(w, 1))) return rc;

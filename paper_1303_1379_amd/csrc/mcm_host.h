@@ -187,8 +187,10 @@ struct RunBufs {
     DevInfo info;
 };
 
-Workspace &workspace(int dev);
-std::mutex &workspace_mutex();
+// The workspace of (device, stream), locked for the caller until `lk` is
+// released: calls on different streams use different workspaces and may
+// overlap (their cooperative launches still take turns at the gate).
+Workspace &acquire_workspace(int dev, const void *stream, std::unique_lock<std::mutex> &lk);
 int64_t ensure_base(Workspace &w, int dev);
 int64_t ensure_graph(Workspace &w, size_t nc, size_t nr, size_t qcap);
 int64_t ensure_desc(Workspace &w, size_t n);

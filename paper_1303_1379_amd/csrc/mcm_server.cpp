@@ -468,8 +468,8 @@ int64_t mcm_server_create(int64_t hbm_budget_bytes, int32_t max_batch, mcm_serve
     };
     if (current_device(&s->dev) || s->dev < 0 || s->dev >= 64) return bail(fail(MCM_EHIP, "no current HIP device"));
     {
-        std::lock_guard<std::mutex> lk(workspace_mutex());
-        Workspace &w = workspace(s->dev);
+        std::unique_lock<std::mutex> lk;
+        Workspace &w = acquire_workspace(s->dev, nullptr, lk);
         int64_t rc;
         if ((rc = ensure_base(w, s->dev))) return bail(rc);
         s->info = w.info;

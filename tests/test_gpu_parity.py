@@ -626,3 +626,39 @@ def test_unsorted_rows_and_duplicates(name):
         assert cards.tolist() == [_oracle_card(g, "empty")] * 2
         assert O.check_matching(g, cm[:g.nc].cpu().numpy(), rm[:g.nr].cpu().numpy()) == cards[0]
     _set(multi_threshold=1 << 15)
+
+
+def test_two_streams_two_threads_small_graphs():
+    """Calls on different streams use separate workspaces and may overlap:
+    two host threads, each on its own stream, match small graphs (the
+    one-workgroup kernel, not a cooperative launch) over and over; every
+    result equals the oracle's."""
+    import threading
+    graphs = [gg.uniform(900, 1000, 3, 40 + i) for i in range(6)]
+    refs = [_oracle_card(g) for g in graphs]
+    dgs = [mcm.to_device(g) for g in graphs]
+    inits = [mcm.cheap_init_host(g.colptr, g.rowind, g.nr) for g in graphs]
+    inits = [(torch.from_numpy(c).cuda(), torch.from_numpy(r).cuda()) for _, c, r in inits]
+    errors = []
+
+    def worker(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for it in range(25):
+                    i = (k + it) % len(graphs)
+                    card, cm, rm = mcm.match(dgs[i], *inits[i], stream=s)
+                    if card != refs[i]:
+                        errors.append((k, it, i, card, refs[i]))
+                    s.synchronize()
+                    if O.check_matching(graphs[i], cm.cpu().numpy(), rm.cpu().numpy()) != card:
+                        errors.append((k, it, i, "invalid"))
+        except Exception as e:  # noqa: BLE001
+            errors.append((k, repr(e)))
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors[:5]
