@@ -560,14 +560,15 @@ DEV void expand_entries(const DevGraph &g, const int4 e, const bool have, uint32
             const int obeg = __shfl(e.z, own, 64);
             const int oexcl = __shfl(excl, own, 64);
             // (every lane takes part in the shuffles: a lane may read an
-            // owner that has no edge of its own in this round)
+            // owner that has no edge of its own in this round, and a
+            // shuffle from a lane outside the branch would read zero)
             const int omate = (flags & F_FASTALT) ? __shfl(cmate, own, 64) : -1;
+            const uint32_t odone = late ? (uint32_t)__shfl((int)rdone, own, 64) : 0u;
             bool newcol = false, newend = false, tried = false;
             int4 ne = make_int4(0, 0, 0, 0);
             int r = 0;
             if (k < total) {
                 r = g.rowind[obeg + (k - oexcl)];
-                const uint32_t odone = late ? (uint32_t)__shfl((int)rdone, own, 64) : 0u;
                 if (!late || odone != ph)
                     visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend, tried, omate);
             }
@@ -808,7 +809,10 @@ DEV void async_bfs(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t 
 // it.  With a root list (g.rlist), phase `ph` also lists its roots in half
 // ph & 1, and from the second phase on scans only the previous phase's
 // list: a matched column never becomes unmatched again, so the roots of a
-// phase are among those of the one before.
+// phase are among those of the one before.  LIST compiles the list in (the
+// launch for one graph); the other launches scan every column and spare the
+// registers.
+template <bool LIST = false>
 DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const RunOpt &o, uint32_t *cnt, Stage &st,
                     uint32_t *s_tmp, Acc &acc, uint64_t *c64 = nullptr, uint32_t ph = 1, uint32_t *ctrl = nullptr)
 {
@@ -818,7 +822,7 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
     const int lane = __lane_id();
     const uint32_t flags = o.flags;
     const uint32_t nc = (uint32_t)g.nc;
-    const bool listed = g.rlist && ctrl;
+    const bool listed = LIST && g.rlist && ctrl;
     int32_t *rl_out = listed ? g.rlist + (size_t)(ph & 1) * nc : nullptr;
     uint32_t *rl_cnt = listed ? line(ctrl, (ph & 1) ? L_NRL1 : L_NRL0) : nullptr;
     const int32_t *rl_in = listed && ph > 1 ? g.rlist + (size_t)((ph - 1) & 1) * nc : nullptr;
@@ -1390,7 +1394,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             // level-free phase: roots reserved in the phase-long queue, one
             // grid barrier, then every wavefront works until the queue's
             // entries are all finished
-            init_roots(g, wave, nwaves, o, nullptr, st, s_tmp, acc, reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)), ph,
+            init_roots<SINGLE>(g, wave, nwaves, o, nullptr, st, s_tmp, acc, reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)), ph,
                        ctrl);
             if (!sync_all(none)) return false;
             async_bfs<WAVE>(g, ctrl, o, ph, nwaves, st, acc);
@@ -1398,7 +1402,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             if (!sync_all(none)) return false;
             s = LvState{0, 0, 0};
         } else {
-        init_roots(g, wave, nwaves, o, fc(0), st, s_tmp, acc, nullptr, ph, ctrl);
+        init_roots<SINGLE>(g, wave, nwaves, o, fc(0), st, s_tmp, acc, nullptr, ph, ctrl);
         if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
         for (;;) {
             const int L = (int)s.L;
@@ -1691,6 +1695,13 @@ __global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *desc
     __shared__ int s_ok;
     __shared__ uint32_t s_loc[16];  // [0..7] level counters, [8..13] barrier state
     __shared__ uint64_t s_acc[kAccN];
+    // Forms this launch never runs, masked so that their code is dead: the
+    // statistics (callers read them from other launches' control blocks),
+    // level records, and the claim, flush, Alternate and BFS forms whose
+    // buffers (radj, prow, checked queues) a batch descriptor does not carry.
+    // The kernel sits at the 128-register limit of a 1024-thread block;
+    // without this its registers spill.
+    o.flags &= ~(uint32_t)(F_STATS | F_LEVELS | F_NOAUG | F_MAXCLAIM | F_DEFER | F_FASTALT | F_ASYNC);
     const uint32_t q = blockIdx.x / group;
     const Grp gr{blockIdx.x % group, group};
     uint32_t *ctrl = ctrls + (size_t)q * L_NLINES * kLineWords;
