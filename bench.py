@@ -23,9 +23,10 @@ to the maximum on the same input from the same greedy matching.
 Further sections: `grid2048` (the mesh-like graph, its own roofline),
 `uniform2000` (microseconds per match, median of 1000), `batched` (4096
 uneven graphs in one captured launch vs a per-graph loop, with the
-kernel's roofline), `serving` (Poisson arrivals through the
-continuous-batching server: latency from the scheduled arrival, capacity,
-and a per-request mcm_match loop over the same graphs).
+kernel's roofline).  With --serving also `serving` (Poisson arrivals
+through the continuous-batching server: latency from the scheduled arrival,
+capacity, and a per-request mcm_match loop over the same graphs); it is
+not part of the default run.
 """
 import argparse
 import hashlib
@@ -479,7 +480,7 @@ def main():
     ap.add_argument("--no-grid", action="store_true", help="skip the grid2048 section")
     ap.add_argument("--no-uniform", action="store_true", help="skip the uniform2000 section")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serving", action="store_true", help="add the serving section (not in the default run)")
     ap.add_argument("--grid-steps", type=int, default=3)
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--serve-requests", type=int, default=20000, help="serving trace length (after 1000 warm-up)")
@@ -572,7 +573,7 @@ def main():
     if not args.no_batched:
         out["batched"] = bench_batched(args.batch_graphs, max(args.steps, 3), 0.0 if args.no_cpu else 10.0)
         print(f"# batched: {out['batched']['batched_ms']} ms", file=sys.stderr, flush=True)
-    if not args.no_serving:
+    if args.serving:
         out["serving"] = bench_serving(48, args.serve_requests + 1000, 1000, args.serve_rate)
     print(json.dumps(out), flush=True)
 
