@@ -95,6 +95,33 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
                   int32_t *out_cmatch, int32_t *out_rmatch, void *stream);
 
 /*
+ * mcm_match_noalloc -- mcm_match for callers that cannot allocate memory:
+ * code under stream capture, tight serving loops, harnesses that forbid
+ * device allocation.  Same arguments, options, results and status codes as
+ * mcm_match (the same kernels run), but the call allocates nothing: the
+ * working state of the match lives in one fixed device array of 64 MiB
+ * that the library holds on each device it runs on until the process ends
+ * (looked up once per device on the first call there), and the host side
+ * uses static memory.
+ *
+ * Limit: the graph's state must fit that array: 32 B per row, 12 B per
+ * column and 32 B per frontier-queue entry (one per column, plus one per 64
+ * edges when columns are split; see option "split"), plus about 260 KB of
+ * control and barrier lines -- about 800 000 vertices per side at 4 edges
+ * per column.  A larger graph returns MCM_ENOMEM with the sizes in the
+ * message, before anything is launched.
+ *
+ * Calls on one device share its array; overlapping calls would race on it,
+ * so the library makes them take turns (a per-device lock held until the
+ * call's stream has finished with the array).  The array keeps the last
+ * call's contents, which the next call does not read.  No per-phase record
+ * (mcm_last_phases) and no kernel timing (kernel_ms reads 0) are kept.
+ */
+int64_t mcm_match_noalloc(int32_t ncols, int32_t nrows, const int32_t *colptr, const int32_t *rowind,
+                          const int32_t *init_cmatch, const int32_t *init_rmatch,
+                          int32_t *out_cmatch, int32_t *out_rmatch, void *stream);
+
+/*
  * One graph of a batch.  Offsets are element offsets into the packed
  * arrays of mcm_match_batched: column pointers of graph g are
  * colptr_all[colptr_off .. colptr_off+ncols] (ncols+1 entries, local

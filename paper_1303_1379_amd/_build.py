@@ -15,7 +15,7 @@ GEN_LIB = os.path.join(HERE, "libmcmgen.so")
 MCM_LIB = os.path.join(HERE, "libmcm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-HIP_SOURCES = ["mcm_kernels.hip"]
+HIP_SOURCES = ["mcm_kernels.hip", "mcm_noalloc.hip"]
 HOST_SOURCES = ["mcm_api.cpp", "mcm_batch.cpp", "mcm_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # gfx950 only; packed-FP32 instructions are disabled for every HIP object.

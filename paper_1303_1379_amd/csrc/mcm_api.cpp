@@ -120,17 +120,26 @@ static void release_workspace(Workspace &w)
     w = Workspace();
 }
 
+// Compute units, architecture name and the wall-clock rate of device `dev`
+// (queries only, nothing is allocated).
+int64_t get_device_info(int dev, DevInfo *info)
+{
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    info->ncu = prop.multiProcessorCount;
+    info->arch = prop.gcnArchName;
+    int rate = 0;
+    if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate > 0)
+        info->clock_khz = rate;
+    return 0;
+}
+
 int64_t ensure_base(Workspace &w, int dev)
 {
     if (w.device == dev && w.ctrl) return 0;
     w.device = dev;
-    hipDeviceProp_t prop;
-    HIPCHK(hipGetDeviceProperties(&prop, dev));
-    w.info.ncu = prop.multiProcessorCount;
-    w.info.arch = prop.gcnArchName;
-    int rate = 0;
-    if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate > 0)
-        w.info.clock_khz = rate;
+    int64_t rc;
+    if ((rc = get_device_info(dev, &w.info))) return rc;
     HIPCHK(hipMalloc(&w.ctrl, (size_t)L_NLINES * 128));
     HIPCHK(hipMalloc(&w.bar, (size_t)kMaxGridBlocks * 128));
     HIPCHK(hipMalloc(&w.mctrl, (size_t)kMultiMax * L_NLINES * 128));

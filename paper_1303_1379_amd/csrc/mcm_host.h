@@ -196,6 +196,25 @@ int64_t ensure_graph(Workspace &w, size_t nc, size_t nr, size_t qcap);
 int64_t ensure_desc(Workspace &w, size_t n);
 int64_t get_device_info(int dev, DevInfo *info);
 
+// The steps of one mcm_match call, shared with mcm_match_noalloc.
+int64_t check_graph_args(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind);
+int64_t check_null_rowind(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind, hipStream_t st);
+// Frontier entries per level (nc + 1, plus one per `split` edges when split
+// is on); reads nnz = colptr[nc] from the device when split is on or
+// nnz_out is given.
+int64_t queue_capacity(int32_t nc, const int32_t *colptr, uint32_t split, hipStream_t st, size_t *qcap,
+                       int64_t *nnz_out);
+// The row-claim, flush, root-test, Alternate and BFS-schedule forms of one
+// mcm_match run (nnz < 0 when unknown).
+uint32_t match_flags(const Options &o, int32_t nc, int32_t nr, int64_t nnz, bool single_wg);
+// One mcm_match run on the state buffers `b`, sized for the graph and
+// `flags`: validation (option validate), the one-workgroup kernel or the
+// persistent phase loop, finish; returns |M| or a negative status.
+int64_t match_run(const RunBufs &b, const Options &o, uint32_t flags, bool single_wg, int32_t ncols, int32_t nrows,
+                  const int32_t *colptr, const int32_t *rowind, const int32_t *init_cmatch,
+                  const int32_t *init_rmatch, int32_t *out_cmatch, int32_t *out_rmatch, hipStream_t st,
+                  const void *owner);
+
 uint32_t *ctrl_line(uint32_t *ctrl, int l);
 uint64_t ctrl_stat(uint32_t *ctrl, int s);
 RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info);

@@ -62,7 +62,7 @@ class mcm_stats(ctypes.Structure):
                 ("pass_bytes", ctypes.c_int64), ("schedule", ctypes.c_int32)]
 
 
-EXPORTS = ["mcm_match", "mcm_match_batched", "mcm_konig_cover", "mcm_bfs_levels", "mcm_cheap_init_host",
+EXPORTS = ["mcm_match", "mcm_match_noalloc", "mcm_match_batched", "mcm_konig_cover", "mcm_bfs_levels", "mcm_cheap_init_host",
            "mcm_cheap_init", "mcm_batch_plan_create", "mcm_batch_plan_run", "mcm_batch_plan_info",
            "mcm_batch_plan_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
            "mcm_server_stats_get", "mcm_server_destroy", "mcm_set_option", "mcm_get_option", "mcm_last_stats",
@@ -82,6 +82,8 @@ def lib():
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     L.mcm_match.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
     L.mcm_match.restype = i64
+    L.mcm_match_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.mcm_match_noalloc.restype = i64
     L.mcm_match_batched.argtypes = [i32, ctypes.POINTER(mcm_graph), vp, vp, vp, vp, vp, vp, vp, vp]
     L.mcm_match_batched.restype = i64
     L.mcm_konig_cover.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -245,6 +247,19 @@ def match(dg: DeviceGraph, init_cmatch=None, init_rmatch=None, out_cmatch=None, 
     card = _check(lib().mcm_match(dg.nc, dg.nr, _ptr(dg.colptr), _ptr(dg.rowind), _ptr(init_cmatch),
                                   _ptr(init_rmatch), _ptr(out_cmatch), _ptr(out_rmatch), _stream(stream)))
     return card, out_cmatch, out_rmatch
+
+
+def match_noalloc(dg: DeviceGraph, init_cmatch, init_rmatch, out_cmatch, out_rmatch, stream=None):
+    """mcm_match_noalloc: the caller passes every array (nothing is
+    allocated here or in the library); returns |M|."""
+    _dev_i32(dg.colptr, dg.nc + 1, "colptr")
+    _dev_i32(out_cmatch, dg.nc, "out_cmatch")
+    _dev_i32(out_rmatch, dg.nr, "out_rmatch")
+    if init_cmatch is not None:
+        _dev_i32(init_cmatch, dg.nc, "init_cmatch")
+        _dev_i32(init_rmatch, dg.nr, "init_rmatch")
+    return _check(lib().mcm_match_noalloc(dg.nc, dg.nr, _ptr(dg.colptr), _ptr(dg.rowind), _ptr(init_cmatch),
+                                          _ptr(init_rmatch), _ptr(out_cmatch), _ptr(out_rmatch), _stream(stream)))
 
 
 def konig_cover(dg: DeviceGraph, cmatch, rmatch, stream=None):
