@@ -438,6 +438,35 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              in Algorithm 1 (BFS trees are
  *                                              then shortest-path trees; the
  *                                              matching is maximum either way)
+ *   "roots"     "auto" (default) | "list" | "scan"
+ *                                              mcm_match's root scan of a
+ *                                              phase: every column (scan),
+ *                                              or only the previous phase's
+ *                                              roots, listed as they are
+ *                                              found (a matched column never
+ *                                              becomes unmatched); auto =
+ *                                              the list while the previous
+ *                                              phase had at most ncols/16
+ *                                              roots, else every column
+ *   "fix"       "auto" (default) | "list" | "scan"
+ *                                              mcm_match's FixMatching:
+ *                                              every row (scan), or only the
+ *                                              rows the walks of the phase
+ *                                              wrote or stopped at (list,
+ *                                              and auto; every row when more
+ *                                              rows were reported than nrows)
+ *   "schedule"  "levels" (default) | "async" | "auto"
+ *                                              mcm_match's BFS under APFB:
+ *                                              level-synchronous, or
+ *                                              level-free (one phase-long
+ *                                              queue, no grid barrier between
+ *                                              levels; measured slower, see
+ *                                              the design notes); auto =
+ *                                              levels
+ *   "keep", "take"  "128", "64" (defaults)     level-free BFS: entries a
+ *                                              wavefront keeps before
+ *                                              handing older ones on (1..192),
+ *                                              and expands per step (1..64)
  *   "validate"  "0" (default) | "1"            check CSC and init on device
  *   "stats"     "0" (default) | "1"            count scanned edges etc.
  *   "tuning"    path of an autotuner cache file (JSON lines) or ""

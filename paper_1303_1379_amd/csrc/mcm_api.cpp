@@ -294,6 +294,10 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     r.local_levels = (uint32_t)o.local_levels;
     r.take = (uint32_t)std::min(o.take, 64);
     r.keep = (uint32_t)std::max(o.keep, o.take);
+    // roots=list: always the list; auto: while the previous phase had at most
+    // nc/16 roots (a listed root costs three gathered words, a scanned column
+    // 12 streamed bytes)
+    r.roots_max = o.roots == 1 ? 0xffffffffu : (uint32_t)std::min<int64_t>(nc / 16, 0xffffffff);
     r.timeout = (uint64_t)(o.timeout_s * info.clock_khz * 1000.0);
     return r;
 }
@@ -515,9 +519,10 @@ uint32_t match_flags(const Options &o, int32_t nc, int32_t nr, int64_t nnz, bool
     // and store per claim cost more than their short walks save, and without
     // WR (many ends per tree) walks would repeat their shared ways.
     if (!single_wg && (o.alternate == 1 || (o.alternate == 2 && low_degree && o.wr))) flags |= F_FASTALT;
-    // Level-free BFS (APFB on the device loop only): no grid barrier between
-    // BFS levels; the deferred level forms do not apply then.
-    if (!single_wg && !o.apsb && o.loop != 1 && o.schedule != 0) {
+    // Level-free BFS (APFB on the device loop only, on request: measured
+    // slower than the level loop on grid2048 by 14x): no grid barrier
+    // between BFS levels; the deferred level forms do not apply then.
+    if (!single_wg && !o.apsb && o.loop != 1 && o.schedule == 1) {
         flags |= F_ASYNC;
         flags &= ~(uint32_t)F_DEFER;
     }

@@ -109,6 +109,8 @@ struct RunOpt {
                            // level ends (0 = strictly level-synchronous)
     uint32_t keep;         // level-free BFS: a wavefront keeps at most this many entries (hands older ones on)
     uint32_t take;         // level-free BFS: entries of its own a wavefront expands per step (1..64, <= keep)
+    uint32_t roots_max;    // with a root list: a phase scans the previous phase's roots only when there are at
+                           // most this many (else every column; reading a listed root gathers three words)
     uint64_t timeout;      // wall-clock ticks a grid barrier may wait
 };
 

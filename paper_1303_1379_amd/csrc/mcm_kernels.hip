@@ -806,14 +806,25 @@ DEV void async_bfs(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uint32_t 
 // Algorithm 4): every unmatched column with at least one edge becomes a
 // root and an entry of the first frontier.  Columns without edges can never
 // be matched and would expand nothing.  Every thread of the workgroup calls
-// it.  With a root list (g.rlist), phase `ph` also lists its roots in half
-// ph & 1, and from the second phase on scans only the previous phase's
-// list: a matched column never becomes unmatched again, so the roots of a
-// phase are among those of the one before.  LIST compiles the list in (the
-// launch for one graph); the other launches scan every column and spare the
-// registers.
+// it.
+//
+// Root lists (LIST, the launch for one graph, with g.rlist): a matched
+// column never becomes unmatched again, so the roots of a phase are among
+// those of the one before.  A phase whose predecessor had at most
+// o.roots_max roots ("active"; phase 1: whose initial matching left at most
+// that many columns unmatched) lists its roots in half ph & 1 of g.rlist;
+// an active phase whose predecessor was active too scans only that
+// predecessor's list instead of every column.  Reading a listed root
+// gathers three words, so with many roots scanning every column is
+// cheaper, and writing a list that the next phase would not read is
+// skipped.  Every phase counts its roots in the low 31 bits of
+// L_NRL0/L_NRL1 (by phase parity); bit 31 marks an active phase.  The
+// count is also every workgroup's place in the list (atomicAdd), so the
+// caller sets the mark only after the grid barrier that ends the scan
+// (mark_active_phase).  Returns whether the phase is active.  The other
+// launches scan every column and spare the registers.
 template <bool LIST = false>
-DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const RunOpt &o, uint32_t *cnt, Stage &st,
+DEV bool init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const RunOpt &o, uint32_t *cnt, Stage &st,
                     uint32_t *s_tmp, Acc &acc, uint64_t *c64 = nullptr, uint32_t ph = 1, uint32_t *ctrl = nullptr)
 {
     // the level-free BFS reserves root slots from its phase-long counter
@@ -822,12 +833,27 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
     const int lane = __lane_id();
     const uint32_t flags = o.flags;
     const uint32_t nc = (uint32_t)g.nc;
-    const bool listed = LIST && g.rlist && ctrl;
-    int32_t *rl_out = listed ? g.rlist + (size_t)(ph & 1) * nc : nullptr;
-    uint32_t *rl_cnt = listed ? line(ctrl, (ph & 1) ? L_NRL1 : L_NRL0) : nullptr;
-    const int32_t *rl_in = listed && ph > 1 ? g.rlist + (size_t)((ph - 1) & 1) * nc : nullptr;
-    // the columns to scan: all, or the previous phase's roots
-    const uint32_t n = rl_in ? ld_u<kAgent>(line(ctrl, ((ph - 1) & 1) ? L_NRL1 : L_NRL0)) : nc;
+    const bool lists = LIST && g.rlist && ctrl;
+    uint32_t *rl_cnt = lists ? line(ctrl, (ph & 1) ? L_NRL1 : L_NRL0) : nullptr;
+    bool active = false, read = false;
+    uint32_t nprev = 0;
+    if (lists) {
+        if (ph > 1) {
+            const uint32_t w = ld_u<kAgent>(line(ctrl, ((ph - 1) & 1) ? L_NRL1 : L_NRL0));
+            nprev = w & 0x7fffffffu;
+            active = nprev <= o.roots_max;
+            read = active && (w >> 31) != 0;
+        } else {
+            const uint64_t m0 = __hip_atomic_load(reinterpret_cast<uint64_t *>(line(ctrl, L_INIT_CARD)),
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            active = (uint64_t)nc - m0 <= (uint64_t)o.roots_max;
+        }
+    }
+    int32_t *rl_out = active ? g.rlist + (size_t)(ph & 1) * nc : nullptr;
+    const int32_t *rl_in = read ? g.rlist + (size_t)((ph - 1) & 1) * nc : nullptr;
+    // the columns to scan: the previous phase's roots, or all of them
+    const uint32_t n = rl_in ? nprev : nc;
+    uint32_t found = 0;  // roots counted without a list (lane 0 of each wavefront)
     // kStream chunks of 64 columns per wavefront and step, their loads
     // issued together (indices clamped, so every load is in bounds and
     // unconditional; a clamped lane is masked afterwards)
@@ -856,11 +882,30 @@ DEV void init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
             }
             if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
             push_entry(p, e, o.split, st, q);
-            if (listed) push_end(p, c, st, rl_out, rl_cnt, q.atomic);
+            if (active) push_end(p, c, st, rl_out, rl_cnt, q.atomic);
+            else if (lists) found += (uint32_t)__popcll(__ballot(p));
         }
     }
     if ((flags & F_STATS) && threadIdx.x == 0 && wave == 0) acc.tick(S_PASS, 4ull * n + nc / 8);
-    block_flush(st, q, listed ? rl_out : g.ends, rl_cnt, s_tmp, false);
+    block_flush(st, q, active ? rl_out : g.ends, rl_cnt, s_tmp, false);
+    if (lists && !active) {
+        // the count of this phase's roots, one addition per workgroup
+        uint32_t *s_cnt = s_tmp + kBatchCtr + 1;
+        if (threadIdx.x == 0) *s_cnt = 0;
+        __syncthreads();
+        if (lane == 0 && found) atomicAdd(s_cnt, found);
+        __syncthreads();
+        if (threadIdx.x == 0 && *s_cnt) atomicAdd(rl_cnt, *s_cnt);
+        __syncthreads();
+    }
+    return active;
+}
+
+// After the grid barrier that ends phase ph's root scan (no workgroup adds
+// to the count any more): mark the phase as active for the next one.
+DEV void mark_active_phase(uint32_t *ctrl, uint32_t ph)
+{
+    atomicOr(line(ctrl, (ph & 1) ? L_NRL1 : L_NRL0), 0x80000000u);
 }
 
 // Alternate (Algorithm 3) from every reached unmatched row, one thread per
@@ -1394,16 +1439,18 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             // level-free phase: roots reserved in the phase-long queue, one
             // grid barrier, then every wavefront works until the queue's
             // entries are all finished
-            init_roots<SINGLE>(g, wave, nwaves, o, nullptr, st, s_tmp, acc, reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)), ph,
-                       ctrl);
+            const bool act = init_roots<SINGLE>(g, wave, nwaves, o, nullptr, st, s_tmp, acc,
+                                                reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)), ph, ctrl);
             if (!sync_all(none)) return false;
+            if (act && leader) mark_active_phase(ctrl, ph);
             async_bfs<WAVE>(g, ctrl, o, ph, nwaves, st, acc);
             ++total_levels;
             if (!sync_all(none)) return false;
             s = LvState{0, 0, 0};
         } else {
-        init_roots<SINGLE>(g, wave, nwaves, o, fc(0), st, s_tmp, acc, nullptr, ph, ctrl);
+        const bool act = init_roots<SINGLE>(g, wave, nwaves, o, fc(0), st, s_tmp, acc, nullptr, ph, ctrl);
         if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
+        if (act && leader) mark_active_phase(ctrl, ph);
         for (;;) {
             const int L = (int)s.L;
             if (s.n == 0 || s.stop) break;
@@ -2006,8 +2053,11 @@ hipError_t launch_setup(const DevGraph &g, const int32_t *ic, const int32_t *ir,
     hipLaunchKernelGGL(k_zero_ctrl, dim3(1), dim3(256), 0, st, ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // at most 1024 blocks: each adds its count of the initial matching to
+    // one word, and same-address atomics serialise (~11 ns each; 8192 blocks
+    // cost ~90 us on an 8 M-vertex graph)
     const int64_t n = g.nc > g.nr ? g.nc : g.nr;
-    hipLaunchKernelGGL(k_setup, dim3(clamp_blocks(n, 256, 256, 8192)), dim3(256), 0, st, g, ic, ir, ctrl, bar, flags);
+    hipLaunchKernelGGL(k_setup, dim3(clamp_blocks(n, 1024, 1, 1024)), dim3(256), 0, st, g, ic, ir, ctrl, bar, flags);
     return hipGetLastError();
 }
 
