@@ -927,16 +927,27 @@ DEV void alternate(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nth
         // for a walk that stops there.
         for (uint32_t i = tid; i < nends; i += nthreads) {
             int r = g.ends[i];
+            int c = ld_i<S>(&g.pred[r]);
+            int r2 = ld_i<S>(&g.prow[r]);
             uint32_t guard = 0;
             for (;;) {
-                const int c = ld_i<S>(&g.pred[r]);
-                const int r2 = ld_i<S>(&g.prow[r]);
+                // the next row's pair is loaded with this column's range
+                // (pred and prow do not change during Alternate)
+                int nc2 = 0, nr2 = -1;
+                if (r2 != -1) {
+                    nc2 = ld_i<S>(&g.pred[r2]);
+                    nr2 = ld_i<S>(&g.prow[r2]);
+                }
+                int2 adj = make_int2(0, 0);
+                if (flags & F_MAXCLAIM) adj = make_int2(g.colptr[c], g.colptr[c + 1]);
                 st_i<S>(&g.cmatch[c], r);
                 st_i<S>(&rlo[2 * (size_t)r], c);
-                if (flags & F_MAXCLAIM) g.radj[r] = make_int2(g.colptr[c], g.colptr[c + 1]);
+                if (flags & F_MAXCLAIM) g.radj[r] = adj;
                 ++steps;
                 if (r2 == -1) break;  // c was a root
                 r = r2;
+                c = nc2;
+                r2 = nr2;
                 if (++guard > (uint32_t)g.nc + 1u) { set_status(ctrl, kEInternal); break; }
             }
         }
@@ -984,25 +995,36 @@ DEV void alternate_listed(const DevGraph &g, uint32_t nends, uint32_t tid, uint3
     const bool fast = (flags & F_FASTALT) != 0;
     uint32_t i = tid, guard = 0;
     bool active = i < nends;
-    int r = 0, c = 0;
-    if (active) {
+    // r: the walk's row; c: its column (pred[r]); fast walks also hold
+    // r2 = prow[r], the next row (pred and prow do not change during
+    // Alternate, so a step loads the next row's pair together with its own
+    // column's range: one round trip per step)
+    int r = 0, c = 0, r2 = -1;
+    auto start = [&]() {
         r = g.ends[i];
-        if (!fast) c = ld_i<S>(&g.pred[r]);
-    }
+        c = ld_i<S>(&g.pred[r]);
+        if (fast) r2 = ld_i<S>(&g.prow[r]);
+    };
+    if (active) start();
     while (__ballot(active)) {
         int touched = -1;
         if (active) {
             bool done = false;
             if (fast) {
-                const int cc = ld_i<S>(&g.pred[r]);
-                const int r2 = ld_i<S>(&g.prow[r]);
-                st_i<S>(&g.cmatch[cc], r);
-                st_i<S>(&rlo[2 * (size_t)r], cc);
-                if (flags & F_MAXCLAIM) g.radj[r] = make_int2(g.colptr[cc], g.colptr[cc + 1]);
+                int nc2 = 0, nr2 = -1;
+                if (r2 != -1) {
+                    nc2 = ld_i<S>(&g.pred[r2]);
+                    nr2 = ld_i<S>(&g.prow[r2]);
+                }
+                int2 adj = make_int2(0, 0);
+                if (flags & F_MAXCLAIM) adj = make_int2(g.colptr[c], g.colptr[c + 1]);
+                st_i<S>(&g.cmatch[c], r);
+                st_i<S>(&rlo[2 * (size_t)r], c);
+                if (flags & F_MAXCLAIM) g.radj[r] = adj;
                 ++steps;
                 touched = r;
                 if (r2 == -1) done = true;
-                else r = r2;
+                else { r = r2; c = nc2; r2 = nr2; }
             } else {
                 const int r2 = ld_i<S>(&g.cmatch[c]);
                 const int c2 = r2 != -1 ? ld_i<S>(&g.pred[r2]) : -1;
@@ -1023,10 +1045,7 @@ DEV void alternate_listed(const DevGraph &g, uint32_t nends, uint32_t tid, uint3
                 i += nthreads;
                 guard = 0;
                 active = i < nends;
-                if (active) {
-                    r = g.ends[i];
-                    if (!fast) c = ld_i<S>(&g.pred[r]);
-                }
+                if (active) start();
             }
         }
         push_end(touched >= 0, touched, st, g.touched, tcnt, true, (uint32_t)g.nr);
