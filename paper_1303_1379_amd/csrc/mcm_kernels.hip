@@ -833,6 +833,36 @@ DEV bool init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
     const int lane = __lane_id();
     const uint32_t flags = o.flags;
     const uint32_t nc = (uint32_t)g.nc;
+    if constexpr (!LIST) {
+        // Every column, one pass: roots staged per wavefront and reserved
+        // per stage drain (the launches for many graphs, whose register
+        // budget has no room for the two-pass form below).
+        for (uint32_t base = wave * 64u * kStream; base < nc; base += nwaves * 64u * kStream) {
+            int cm[kStream], b[kStream], en[kStream];
+#pragma unroll
+            for (int u = 0; u < kStream; ++u) {
+                const uint32_t c = min(base + 64u * u + (uint32_t)lane, nc - 1);
+                cm[u] = g.cmatch[c];
+                b[u] = g.colptr[c];
+                en[u] = g.colptr[c + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kStream; ++u) {
+                const uint32_t c = base + 64u * u + (uint32_t)lane;
+                const bool in = c < nc, un = in && cm[u] == -1;
+                const bool p = un && en[u] > b[u];
+                if ((flags & F_LEVELS) && in) {
+                    g.clevel[c] = un ? 0 : -1;
+                    if (g.croot) g.croot[c] = un ? (int)c : -1;
+                }
+                if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
+                push_entry(p, make_int4((int)c, (int)c, b[u], en[u]), o.split, st, q);
+            }
+        }
+        if ((flags & F_STATS) && threadIdx.x == 0 && wave == 0) acc.tick(S_PASS, 4ull * nc + nc / 8);
+        block_flush(st, q, g.ends, nullptr, s_tmp, false);
+        return false;
+    }
     const bool lists = LIST && g.rlist && ctrl;
     uint32_t *rl_cnt = lists ? line(ctrl, (ph & 1) ? L_NRL1 : L_NRL0) : nullptr;
     bool active = false, read = false;
@@ -853,51 +883,98 @@ DEV bool init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
     const int32_t *rl_in = read ? g.rlist + (size_t)((ph - 1) & 1) * nc : nullptr;
     // the columns to scan: the previous phase's roots, or all of them
     const uint32_t n = rl_in ? nprev : nc;
-    uint32_t found = 0;  // roots counted without a list (lane 0 of each wavefront)
+    const uint32_t split = o.split;
+    // Two passes over the same columns: the first counts the frontier
+    // entries (a root of more than `split` edges enters as several) and the
+    // roots, one reservation per workgroup follows, and the second writes
+    // entries (and listed roots) at their places.  One counter atomic per
+    // workgroup instead of one per wavefront stage drain: with millions of
+    // roots (rmat23) the drains' same-address atomics dominated the scan.
     // kStream chunks of 64 columns per wavefront and step, their loads
     // issued together (indices clamped, so every load is in bounds and
-    // unconditional; a clamped lane is masked afterwards)
-    for (uint32_t base = wave * 64u * kStream; base < n; base += nwaves * 64u * kStream) {
-        int col[kStream], cm[kStream], b[kStream], en[kStream];
+    // unconditional; a clamped lane is masked afterwards).
+    auto scan = [&](auto &&visit) {
+        for (uint32_t base = wave * 64u * kStream; base < n; base += nwaves * 64u * kStream) {
+            int col[kStream], cm[kStream], b[kStream], en[kStream];
 #pragma unroll
-        for (int u = 0; u < kStream; ++u) {
-            const uint32_t i = min(base + 64u * u + (uint32_t)lane, n - 1);
-            col[u] = rl_in ? rl_in[i] : (int)i;
-        }
-#pragma unroll
-        for (int u = 0; u < kStream; ++u) {
-            cm[u] = g.cmatch[col[u]];
-            b[u] = g.colptr[col[u]];
-            en[u] = g.colptr[col[u] + 1];
-        }
-#pragma unroll
-        for (int u = 0; u < kStream; ++u) {
-            const int c = col[u];
-            const bool in = base + 64u * u + (uint32_t)lane < n, un = in && cm[u] == -1;
-            const bool p = un && en[u] > b[u];
-            const int4 e = make_int4(c, c, b[u], en[u]);
-            if ((flags & F_LEVELS) && in) {
-                g.clevel[c] = un ? 0 : -1;
-                if (g.croot) g.croot[c] = un ? c : -1;
+            for (int u = 0; u < kStream; ++u) {
+                const uint32_t i = min(base + 64u * u + (uint32_t)lane, n - 1);
+                col[u] = rl_in ? rl_in[i] : (int)i;
             }
-            if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
-            push_entry(p, e, o.split, st, q);
-            if (active) push_end(p, c, st, rl_out, rl_cnt, q.atomic);
-            else if (lists) found += (uint32_t)__popcll(__ballot(p));
+#pragma unroll
+            for (int u = 0; u < kStream; ++u) {
+                cm[u] = g.cmatch[col[u]];
+                b[u] = g.colptr[col[u]];
+                en[u] = g.colptr[col[u] + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kStream; ++u) {
+                const bool in = base + 64u * u + (uint32_t)lane < n, un = in && cm[u] == -1;
+                const bool p = un && en[u] > b[u];
+                const uint32_t deg = p ? (uint32_t)(en[u] - b[u]) : 0u;
+                const uint32_t nent = p ? ((split && deg > split) ? (deg + split - 1) / split : 1u) : 0u;
+                visit(col[u], in, un, p, b[u], en[u], nent);
+            }
         }
+    };
+    // pass 1: entries and roots of this wavefront (uniform sums)
+    uint32_t went = 0, wroots = 0;
+    scan([&](int, bool, bool, bool p, int, int, uint32_t nent) {
+        went += (uint32_t)wave_sum((uint64_t)nent);
+        wroots += (uint32_t)__popcll(__ballot(p));
+    });
+    // reservation: wavefront offsets by a scan in the workgroup, one atomic
+    // per workgroup on the frontier counter and one on the root count
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) { s_tmp[w] = went; s_tmp[16 + w] = wroots; }
+    __syncthreads();
+    if (w == 0) {
+        const int a = lane < nw ? (int)s_tmp[lane] : 0, r = lane < nw ? (int)s_tmp[16 + lane] : 0;
+        const int ia = wave_incl_scan(a), ir = wave_incl_scan(r);
+        const uint32_t ta = (uint32_t)__shfl(ia, 63, 64), tr = (uint32_t)__shfl(ir, 63, 64);
+        uint32_t qb = 0, rb = 0;
+        if (lane == 0) {
+            if (ta) qb = q.c64 ? (uint32_t)__hip_atomic_fetch_add(q.c64, (uint64_t)ta, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT)
+                               : atomicAdd(q.c32, ta);
+            if (tr && lists) rb = atomicAdd(rl_cnt, tr);
+        }
+        qb = (uint32_t)__shfl((int)qb, 0, 64);
+        rb = (uint32_t)__shfl((int)rb, 0, 64);
+        if (lane < nw) { s_tmp[32 + lane] = qb + (uint32_t)(ia - a); s_tmp[48 + lane] = rb + (uint32_t)(ir - r); }
     }
+    __syncthreads();
+    uint32_t qoff = s_tmp[32 + w], roff = s_tmp[48 + w];
+    __syncthreads();
+    // words 32..63 of s_tmp served the offsets; the level batch counter
+    // among them starts every level at zero
+    if (threadIdx.x == 0) s_tmp[kBatchCtr] = 0;
+    // pass 2: the same columns, written at their places
+    scan([&](int c, bool in, bool un, bool p, int b, int en, uint32_t nent) {
+        const int incl = wave_incl_scan((int)nent);
+        uint32_t at = qoff + (uint32_t)(incl - (int)nent);
+        for (uint32_t k = 0; k < nent; ++k) {
+            const int eb = b + (int)(k * split);
+            const int ee = (nent > 1 && eb + (int)split < en) ? eb + (int)split : en;
+            put_entry(q, at + k, make_int4(c, c, eb, ee));
+        }
+        qoff += (uint32_t)__shfl(incl, 63, 64);
+        const uint64_t m = __ballot(p);
+        if (active && p) put_end(rl_out, roff + (uint32_t)__popcll(m & lanemask_lt()), c, q.atomic);
+        roff += (uint32_t)__popcll(m);
+        if ((flags & F_LEVELS) && in) {
+            g.clevel[c] = un ? 0 : -1;
+            if (g.croot) g.croot[c] = un ? c : -1;
+        }
+        if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
+    });
     if ((flags & F_STATS) && threadIdx.x == 0 && wave == 0) acc.tick(S_PASS, 4ull * n + nc / 8);
-    block_flush(st, q, active ? rl_out : g.ends, rl_cnt, s_tmp, false);
-    if (lists && !active) {
-        // the count of this phase's roots, one addition per workgroup
-        uint32_t *s_cnt = s_tmp + kBatchCtr + 1;
-        if (threadIdx.x == 0) *s_cnt = 0;
-        __syncthreads();
-        if (lane == 0 && found) atomicAdd(s_cnt, found);
-        __syncthreads();
-        if (threadIdx.x == 0 && *s_cnt) atomicAdd(rl_cnt, *s_cnt);
-        __syncthreads();
-    }
+    // nothing staged, and nothing counted as drained for the first level's
+    // flush (its count of entries and its "reached an unmatched row" bit,
+    // which stops an APsB level loop, start from zero here)
+    st.nq = st.ne = 0;
+    st.dq = st.de = 0;
+    __syncthreads();
     return active;
 }
 
@@ -1051,6 +1128,7 @@ DEV void alternate_listed(const DevGraph &g, uint32_t nends, uint32_t tid, uint3
         push_end(touched >= 0, touched, st, g.touched, tcnt, true, (uint32_t)g.nr);
     }
     if (st.ne) drain_ends(st, g.touched, tcnt, true, (uint32_t)g.nr);
+    st.de = 0;  // the reports are no level's unmatched rows
     if (flags & F_STATS) acc.add(S_ALT, steps);
 }
 
