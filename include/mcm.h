@@ -452,9 +452,11 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              mcm_match's FixMatching:
  *                                              every row (scan), or only the
  *                                              rows the walks of the phase
- *                                              wrote or stopped at (list,
- *                                              and auto; every row when more
- *                                              rows were reported than nrows)
+ *                                              wrote or stopped at (list;
+ *                                              every row when more rows were
+ *                                              reported than nrows); auto =
+ *                                              the list in phases that found
+ *                                              at most nrows/64 ends
  *   "schedule"  "levels" (default) | "async" | "auto"
  *                                              mcm_match's BFS under APFB:
  *                                              level-synchronous, or

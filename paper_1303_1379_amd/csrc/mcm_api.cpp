@@ -298,6 +298,7 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     // nc/16 roots (a listed root costs three gathered words, a scanned column
     // 12 streamed bytes)
     r.roots_max = o.roots == 1 ? 0xffffffffu : (uint32_t)std::min<int64_t>(nc / 16, 0xffffffff);
+    r.fix_max = 0xffffffffu;  // run_graph sets the rows-based bound of fix=auto
     r.timeout = (uint64_t)(o.timeout_s * info.clock_khz * 1000.0);
     return r;
 }
@@ -313,6 +314,10 @@ int64_t run_graph(const RunBufs &b, const Options &o, const DevGraph &g, uint32_
     *loop_used = loop;
     if (loop != 0) flags &= ~(uint32_t)F_DEFER;  // deferred writes belong to the persistent level loop
     RunOpt ro = run_opt(o, flags, g.nc, b.info);
+    // fix=auto: reporting walk rows costs a same-address atomic per 64
+    // reports, scanning every row 12 streamed bytes per row; list while a
+    // phase has at most nr/64 ends (rmat23's first phase has ~800 000)
+    if (o.fix == 2) ro.fix_max = (uint32_t)(g.nr / 64);
     if (loop == 0) {
         int occ = 0;
         HIPCHK(persistent_occupancy(wave, o.block, &occ));

@@ -92,7 +92,8 @@ struct Options {
     int local_levels = 6;     // grid levels: a wavefront expands its own new entries this many times more
     int alternate = 2;        // mcm_match's Alternate: 0 classic, 1 recorded rows, 2 auto (1 on low degree)
     int schedule = 0;         // mcm_match's BFS: 0 level-synchronous, 1 level-free, 2 auto (= 0)
-    int fix = 2;              // mcm_match's FixMatching: 0 every row, 1 the rows the walks touched, 2 auto (1)
+    int fix = 2;              // mcm_match's FixMatching: 0 every row, 1 the rows the walks touched, 2 auto (1 in
+                              // phases with at most nr/64 ends, else 0)
     int keep = 128;           // level-free BFS: entries a wavefront keeps before handing older ones on
     int take = 64;            // level-free BFS: entries of its own a wavefront expands per step
     int roots = 2;            // mcm_match's root scan: 0 every column, 1 the previous phase's roots, 2 auto (1 while

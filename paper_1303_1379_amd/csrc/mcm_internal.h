@@ -111,6 +111,8 @@ struct RunOpt {
     uint32_t take;         // level-free BFS: entries of its own a wavefront expands per step (1..64, <= keep)
     uint32_t roots_max;    // with a root list: a phase scans the previous phase's roots only when there are at
                            // most this many (else every column; reading a listed root gathers three words)
+    uint32_t fix_max;      // with a touched-row list: Alternate reports its rows and FixMatching visits only
+                           // those when the phase found at most this many ends (else every row is scanned)
     uint64_t timeout;      // wall-clock ticks a grid barrier may wait
 };
 

@@ -1598,14 +1598,17 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         }
         if (ne == 0 || (flags & F_NOAUG)) break;
         const uint64_t ta = timing ? wall_clock64() : 0;
-        if (SINGLE && g.touched)
+        // the walks report the rows they touch when the phase found few ends
+        // (o.fix_max); FixMatching then visits only those
+        const bool listed = SINGLE && g.touched && ne <= o.fix_max;
+        if (listed)
             alternate_listed<kAgent>(g, ne, tid, nthreads, flags, ctrl, acc, st, line(ctrl, L_NTOUCH));
         else
             alternate<kAgent>(g, ne, tid, nthreads, SINGLE ? flags : (flags & ~(uint32_t)F_FASTALT), ctrl, acc);
         if (!sync_all(none)) return false;
         // FixMatching over the rows the walks touched, unless more were
         // reported than the list holds (then over every row)
-        const uint32_t ntouch = (SINGLE && g.touched) ? ld_u<kAgent>(line(ctrl, L_NTOUCH)) : 0xffffffffu;
+        const uint32_t ntouch = listed ? ld_u<kAgent>(line(ctrl, L_NTOUCH)) : 0xffffffffu;
         if (ntouch <= (uint32_t)g.nr) {
             fix_listed(g, ntouch, tid, nthreads, flags, acc);
             if (timing && gr.b == 0) acc.tick(S_PASS, 8ull * ntouch);

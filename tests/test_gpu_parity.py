@@ -320,7 +320,7 @@ def test_alternate_forms(alt, combo, name):
 # scan over every column or over the previous phase's roots, with both
 # schedules and both walks; one end per root leaves the other unmatched rows
 # it reaches unmatched at once (no row is left marked for FixMatching).
-@pytest.mark.parametrize("fix", ["scan", "list"])
+@pytest.mark.parametrize("fix", ["scan", "list", "auto"])
 @pytest.mark.parametrize("roots", ["scan", "list", "auto"])
 @pytest.mark.parametrize("form", [dict(schedule="levels", alternate="fast"), dict(schedule="levels", alternate="classic"),
                                   dict(schedule="async", alternate="fast"), dict(schedule="async", alternate="classic"),
