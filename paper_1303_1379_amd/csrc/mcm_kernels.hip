@@ -346,84 +346,126 @@ DEV uint32_t block_flush(Stage &st, const QSink &k, int32_t *ge, uint32_t *gecnt
 // adds the root bookkeeping).  A matched, unvisited row is claimed and its
 // column becomes a next-frontier entry; an unmatched, unvisited row is
 // claimed as an augmenting-path end (rmatch = -2) and marks its root done.
+//
+// The visit runs in three steps so that a lane can keep the memory accesses
+// of several edges in flight together: visit_issue sends the first access
+// to the row's word (the probe, or with F_MAXCLAIM the claim itself),
+// visit_settle the compare-and-swap that follows a probe, visit_finish acts
+// on what came back.  No step waits for its own accesses: the next step (or
+// the same step of another edge) issues first.
+struct Visit {
+    uint64_t w;    // the row word: what the probe read, or what the atomic maximum replaced
+    int2 adj;      // adjacency range of the row's mate
+    int kind;      // 0 nothing to do, 1 probed, 2 claiming as a column, 3 claiming as an end, 4 claimed by maximum
+};
+
 template <int S>
-DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, int level, uint32_t flags,
-                    bool &newcol, int4 &ne, bool &newend, bool &tried, int colmate)
+DEV Visit visit_issue(const DevGraph &g, int r, bool on, uint32_t ph, uint32_t flags)
 {
+    Visit v{0, make_int2(0, 0), 0};
+    if (!on) return v;
     if (flags & F_MAXCLAIM) {
         // Low-degree rows: one atomic maximum of the phase stamp claims the
         // row and returns its old word (a row already stamped this phase is
         // left as it is); the mate's adjacency range comes from radj, loaded
         // alongside.  Stamps only grow during a run, so exactly one visitor
-        // per phase sees an older stamp.  The winner puts the mate (or -2)
-        // back into the low word, which no one reads before the next grid
-        // barrier.
-        const int2 adj = g.radj[r];
-        const uint64_t old = __hip_atomic_fetch_max(&g.rw[r], (uint64_t)ph << 32, __ATOMIC_RELAXED, S);
-        if ((uint32_t)(old >> 32) == ph) return;
-        tried = true;
-        const int mate = (int)(uint32_t)old;
-        int32_t *lo = reinterpret_cast<int32_t *>(g.rw) + 2 * (size_t)r;
-        st_i<S>(&g.pred[r], col);
-        if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
-        if (mate >= 0) {
-            st_i<S>(lo, mate);
-            ne = make_int4(mate, root, adj.x, adj.y);
-            newcol = true;
-            if (flags & F_LEVELS) {
-                g.clevel[mate] = level + 1;
-                if (g.croot) g.croot[mate] = root;
-            }
-        } else {
-            if ((flags & F_WR) && (flags & F_ENDPOINT)) {
-                // one end per root: a row reached after the first stays
-                // unmatched (-1); its stamp keeps it out of this phase
-                newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
-                st_i<S>(lo, newend ? -2 : -1);
-            } else {
-                st_i<S>(lo, -2);
-                newend = true;
-                if (flags & F_WR) st_u<S>(&g.cdone[root], ph);
-            }
-        }
-        return;
+        // per phase sees an older stamp.
+        v.adj = g.radj[r];
+        v.w = __hip_atomic_fetch_max(&g.rw[r], (uint64_t)ph << 32, __ATOMIC_RELAXED, S);
+        v.kind = 4;
+    } else {
+        // agent scope reads the memory-side copy, which other XCDs' claims
+        // update; a stale L2 copy would send every scanner of a popular row
+        // into a failing compare-and-swap
+        v.w = (S == kAgent) ? __hip_atomic_load(&g.rw[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : g.rw[r];
+        v.kind = 1;
     }
-    // agent scope reads the memory-side copy, which other XCDs' claims
-    // update; a stale L2 copy would send every scanner of a popular row
-    // into a failing compare-and-swap
-    const uint64_t w = (S == kAgent) ? __hip_atomic_load(&g.rw[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : g.rw[r];
-    if ((uint32_t)(w >> 32) == ph) return;           // reached earlier in this phase
-    const int mate = (int)(uint32_t)w;
-    tried = mate >= -1;                               // a compare-and-swap follows
-    if (mate >= 0) {
+    return v;
+}
+
+// What the probe found: a row reached earlier in this phase is left alone,
+// an unreached one is claimed as a column (2) or an end (3).
+// (Written without branches: every lane reads its probe's word here, so
+// that no later step waits for it.)
+DEV void visit_decide(Visit &v, uint32_t ph, bool &tried)
+{
+    const int mate = (int)(uint32_t)v.w;
+    const bool claim = v.kind == 1 && (uint32_t)(v.w >> 32) != ph && mate >= -1;
+    v.kind = claim ? (mate >= 0 ? 2 : 3) : (v.kind == 1 ? 0 : v.kind);
+    tried = claim;  // a compare-and-swap follows
+}
+
+// The claim after a probe: a compare-and-swap of the stamp half of the row
+// word alone.  During a phase's BFS a row word changes only by claims, and
+// every claim sets the stamp to the phase, so a stamp still equal to the
+// probed one means an unchanged word.  The mate half stays as it is (an
+// end's winner writes -2 there itself, see visit_finish).  Returns the
+// stamp found (the probed one when the claim won).
+template <int S>
+DEV uint32_t visit_settle(const DevGraph &g, int r, Visit &v, uint32_t ph)
+{
+    if (v.kind != 2 && v.kind != 3) return 0;
+    uint32_t want = (uint32_t)(v.w >> 32);
+    if (v.kind == 2) {
         // adjacency range of the column behind r, fetched alongside the claim
-        const int b = g.colptr[mate], e = g.colptr[mate + 1];
-        if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | (uint32_t)mate)) {
-            st_i<S>(&g.pred[r], col);
-            if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
-            ne = make_int4(mate, root, b, e);
-            newcol = true;
-            if (flags & F_LEVELS) {
-                g.clevel[mate] = level + 1;
-                if (g.croot) g.croot[mate] = root;
-            }
-        }
-    } else if (mate == -1) {
-        if (cas_u64<S>(&g.rw[r], w, ((uint64_t)ph << 32) | 0xFFFFFFFEull)) {
-            st_i<S>(&g.pred[r], col);
-            if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
-            if ((flags & F_WR) && (flags & F_ENDPOINT)) {
-                // the root's path ends at the first unmatched row it reached;
-                // a later one returns to unmatched (-1), its stamp keeping it
-                // out of this phase
-                newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
-                if (!newend) st_i<S>(reinterpret_cast<int32_t *>(g.rw) + 2 * (size_t)r, -1);
-            } else {
-                newend = true;
-                if (flags & F_WR) st_u<S>(&g.cdone[root], ph);
-            }
-        }
+        const int mate = (int)(uint32_t)v.w;
+        v.adj = make_int2(g.colptr[mate], g.colptr[mate + 1]);
     }
+    __hip_atomic_compare_exchange_strong(reinterpret_cast<uint32_t *>(g.rw) + 2 * (size_t)r + 1, &want, ph,
+                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED, S);
+    return want;  // the stamp found: the probed one when the exchange happened
+}
+
+// Whether the visit claimed its row; `found` is what visit_settle returned.
+DEV bool visit_won(const Visit &v, uint32_t found, uint32_t ph)
+{
+    if (v.kind == 4) return (uint32_t)(v.w >> 32) != ph;
+    return (v.kind == 2 || v.kind == 3) && found == (uint32_t)(v.w >> 32);
+}
+
+template <int S>
+DEV void visit_finish(const DevGraph &g, int col, int root, int r, const Visit &v, bool won, uint32_t ph,
+                      int level, uint32_t flags, bool &newcol, int4 &ne, bool &newend, bool &tried, int colmate)
+{
+    if (!won) return;
+    if (v.kind == 4) tried = true;
+    const int mate = (int)(uint32_t)v.w;  // -1 for an end
+    // The winner writes the low word (which no one reads before the next
+    // grid barrier): an atomic maximum left 0 there, so the mate goes back;
+    // an end gets -2 (below, with one end per root, -2 or -1)
+    int32_t *lo = reinterpret_cast<int32_t *>(g.rw) + 2 * (size_t)r;
+    if (v.kind == 4 && mate >= 0) st_i<S>(lo, mate);
+    else if (mate < 0 && !((flags & F_WR) && (flags & F_ENDPOINT))) st_i<S>(lo, -2);
+    st_i<S>(&g.pred[r], col);
+    if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
+    if (mate >= 0) {
+        ne = make_int4(mate, root, v.adj.x, v.adj.y);
+        newcol = true;
+        if (flags & F_LEVELS) {
+            g.clevel[mate] = level + 1;
+            if (g.croot) g.croot[mate] = root;
+        }
+    } else if ((flags & F_WR) && (flags & F_ENDPOINT)) {
+        // the root's path ends at the first unmatched row it reached; a
+        // later one returns to unmatched (-1), its stamp keeping it out of
+        // this phase
+        newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
+        st_i<S>(lo, newend ? -2 : -1);
+    } else {
+        newend = true;
+        if (flags & F_WR) st_u<S>(&g.cdone[root], ph);
+    }
+}
+
+template <int S>
+DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, int level, uint32_t flags,
+                    bool &newcol, int4 &ne, bool &newend, bool &tried, int colmate)
+{
+    Visit v = visit_issue<S>(g, r, true, ph, flags);
+    visit_decide(v, ph, tried);
+    const uint32_t found = visit_settle<S>(g, r, v, ph);
+    visit_finish<S>(g, col, root, r, v, visit_won(v, found, ph), ph, level, flags, newcol, ne, newend, tried,
+                    colmate);
 }
 
 struct LevelIO {
@@ -523,7 +565,7 @@ DEV void push_entry(bool p, const int4 &e, uint32_t split, Stage &st, const QSin
 // claim rows, stage the columns claimed and the unmatched rows reached.
 // Wavefront-uniform call.  `late`: the GPUBFS-WR root test beside each edge
 // visit (wave mapping), else before the scan.
-template <bool WAVE, int S>
+template <bool WAVE, int S, bool PAIR = false>
 DEV void expand_entries(const DevGraph &g, const int4 e, const bool have, uint32_t ph, int level, uint32_t flags,
                         bool late, const RunOpt &o, const LevelIO &io, Stage &st, Acc &acc, bool &any_end)
 {
@@ -546,32 +588,36 @@ DEV void expand_entries(const DevGraph &g, const int4 e, const bool have, uint32
         const int incl = wave_incl_scan(deg);
         const int excl = incl - deg;
         const int total = __shfl(incl, 63, 64);
-        for (int eb = 0; eb < total; eb += 64) {
-            const int k = eb + lane;
-            // owner lane: the largest o with excl[o] <= k (excl is non-decreasing)
-            int own = 0;
+        // owner lane of edge k of the round: the largest o with excl[o] <= k
+        // (excl is non-decreasing); a lane past the last edge takes the last
+        // edge's owner (it visits nothing)
+        auto owner = [&](int k) -> int {
+            const int kk = k < total ? k : total - 1;
+            int ow = 0;
 #pragma unroll
             for (int step = 32; step >= 1; step >>= 1) {
-                const int v = __shfl(excl, own + step, 64);
-                if (v <= k) own += step;
+                const int x = __shfl(excl, ow + step, 64);
+                if (x <= kk) ow += step;
             }
-            const int ocol = __shfl(e.x, own, 64);
-            const int oroot = __shfl(e.y, own, 64);
-            const int obeg = __shfl(e.z, own, 64);
-            const int oexcl = __shfl(excl, own, 64);
-            // (every lane takes part in the shuffles: a lane may read an
-            // owner that has no edge of its own in this round, and a
-            // shuffle from a lane outside the branch would read zero)
-            const int omate = (flags & F_FASTALT) ? __shfl(cmate, own, 64) : -1;
+            return ow;
+        };
+        // the row of edge k (the last edge's past the end)
+        auto row = [&](int k, int own) -> int {
+            const int kk = k < total ? k : total - 1;
+            return g.rowind[__shfl(e.z, own, 64) + (kk - __shfl(excl, own, 64))];
+        };
+        // (every lane takes part in the shuffles: a shuffle from a lane
+        // outside a branch reads zero)
+        auto live = [&](int k, int own) -> bool {
             const uint32_t odone = late ? (uint32_t)__shfl((int)rdone, own, 64) : 0u;
-            bool newcol = false, newend = false, tried = false;
+            return k < total && (!late || odone != ph);
+        };
+        auto finish = [&](int r, int own, const Visit &v, bool won, bool tried) {
+            const int col = __shfl(e.x, own, 64), root = __shfl(e.y, own, 64);
+            const int omate = (flags & F_FASTALT) ? __shfl(cmate, own, 64) : -1;
+            bool newcol = false, newend = false;
             int4 ne = make_int4(0, 0, 0, 0);
-            int r = 0;
-            if (k < total) {
-                r = g.rowind[obeg + (k - oexcl)];
-                if (!late || odone != ph)
-                    visit_edge<S>(g, ocol, oroot, r, ph, level, flags, newcol, ne, newend, tried, omate);
-            }
+            visit_finish<S>(g, col, root, r, v, won, ph, level, flags, newcol, ne, newend, tried, omate);
             push_entry(newcol, ne, o.split, st, io.next);
             push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
             any_end |= newend;
@@ -579,6 +625,50 @@ DEV void expand_entries(const DevGraph &g, const int4 e, const bool have, uint32
                 acc.add(S_CLAIMED, newcol ? 1u : 0u);
                 acc.add(S_FOUND, newend ? 1u : 0u);
                 acc.add(S_TRIES, tried ? 1u : 0u);
+            }
+        };
+        for (int eb = 0; eb < total;) {
+            if (PAIR && !(flags & F_MAXCLAIM) && total - eb > 64) {
+                // Two edges per lane (probe claims): both rows are loaded,
+                // then both probed, then both compared-and-swapped, each
+                // step's two accesses in flight together, so that 128 edges
+                // wait for about as many round trips to memory as 64.  The
+                // probes are plain reads and go out for every lane, with or
+                // without an edge to visit, so that nothing branches between
+                // them.  (The owners are found again after the claims rather
+                // than held in registers through them.)
+                const int k0 = eb + lane, k1 = eb + 64 + lane;
+                int own0 = owner(k0), own1 = owner(k1);
+                const int r0 = row(k0, own0), r1 = row(k1, own1);
+                Visit v0 = visit_issue<S>(g, r0, true, ph, flags);
+                Visit v1 = visit_issue<S>(g, r1, true, ph, flags);
+                if (!live(k0, own0)) v0.kind = 0;
+                if (!live(k1, own1)) v1.kind = 0;
+                // both probes are decided before either claim goes out (the
+                // wavefront's vote on whether any claim follows needs both),
+                // so that no wait for the second probe falls between the
+                // claims; a round of rows all reached before skips them
+                bool t0 = false, t1 = false;
+                visit_decide(v0, ph, t0);
+                visit_decide(v1, ph, t1);
+                uint32_t f0 = 0, f1 = 0;
+                if (__ballot(t0 || t1) != 0) {
+                    f0 = visit_settle<S>(g, r0, v0, ph);
+                    f1 = visit_settle<S>(g, r1, v1, ph);
+                }
+                const bool won0 = visit_won(v0, f0, ph), won1 = visit_won(v1, f1, ph);
+                finish(r0, owner(k0), v0, won0, t0);
+                finish(r1, owner(k1), v1, won1, t1);
+                eb += 128;
+            } else {
+                const int k = eb + lane, own = owner(k);
+                const int r = row(k, own);
+                Visit v = visit_issue<S>(g, r, live(k, own), ph, flags);
+                bool tried = false;
+                visit_decide(v, ph, tried);
+                const uint32_t f = visit_settle<S>(g, r, v, ph);
+                finish(r, own, v, visit_won(v, f, ph), tried);
+                eb += 64;
             }
         }
     } else {
@@ -630,7 +720,7 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
     const bool dyn = (uint64_t)nwaves * B < n;
     uint32_t *ctr = s_tmp + kBatchCtr;
     auto expand = [&](const int4 e, const bool have) {
-        expand_entries<WAVE, S>(g, e, have, ph, level, flags, late, o, io, st, acc, any_end);
+        expand_entries<WAVE, S, SINGLE>(g, e, have, ph, level, flags, late, o, io, st, acc, any_end);
     };
     // one batch of entries [base, base + B) of the frontier
     auto batch = [&](const uint32_t base) {
