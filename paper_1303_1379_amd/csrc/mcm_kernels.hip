@@ -347,125 +347,123 @@ DEV uint32_t block_flush(Stage &st, const QSink &k, int32_t *ge, uint32_t *gecnt
 // column becomes a next-frontier entry; an unmatched, unvisited row is
 // claimed as an augmenting-path end (rmatch = -2) and marks its root done.
 //
-// The visit runs in three steps so that a lane can keep the memory accesses
-// of several edges in flight together: visit_issue sends the first access
-// to the row's word (the probe, or with F_MAXCLAIM the claim itself),
-// visit_settle the compare-and-swap that follows a probe, visit_finish acts
-// on what came back.  No step waits for its own accesses: the next step (or
-// the same step of another edge) issues first.
-struct Visit {
-    uint64_t w;    // the row word: what the probe read, or what the atomic maximum replaced
-    int2 adj;      // adjacency range of the row's mate
-    int kind;      // 0 nothing to do, 1 probed, 2 claiming as a column, 3 claiming as an end, 4 claimed by maximum
-};
-
-template <int S>
-DEV Visit visit_issue(const DevGraph &g, int r, bool on, uint32_t ph, uint32_t flags)
-{
-    Visit v{0, make_int2(0, 0), 0};
-    if (!on) return v;
-    if (flags & F_MAXCLAIM) {
-        // Low-degree rows: one atomic maximum of the phase stamp claims the
-        // row and returns its old word (a row already stamped this phase is
-        // left as it is); the mate's adjacency range comes from radj, loaded
-        // alongside.  Stamps only grow during a run, so exactly one visitor
-        // per phase sees an older stamp.
-        v.adj = g.radj[r];
-        v.w = __hip_atomic_fetch_max(&g.rw[r], (uint64_t)ph << 32, __ATOMIC_RELAXED, S);
-        v.kind = 4;
-    } else {
-        // agent scope reads the memory-side copy, which other XCDs' claims
-        // update; a stale L2 copy would send every scanner of a popular row
-        // into a failing compare-and-swap
-        v.w = (S == kAgent) ? __hip_atomic_load(&g.rw[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : g.rw[r];
-        v.kind = 1;
-    }
-    return v;
-}
-
-// What the probe found: a row reached earlier in this phase is left alone,
-// an unreached one is claimed as a column (2) or an end (3).
-// (Written without branches: every lane reads its probe's word here, so
-// that no later step waits for it.)
-DEV void visit_decide(Visit &v, uint32_t ph, bool &tried)
-{
-    const int mate = (int)(uint32_t)v.w;
-    const bool claim = v.kind == 1 && (uint32_t)(v.w >> 32) != ph && mate >= -1;
-    v.kind = claim ? (mate >= 0 ? 2 : 3) : (v.kind == 1 ? 0 : v.kind);
-    tried = claim;  // a compare-and-swap follows
-}
-
-// The claim after a probe: a compare-and-swap of the stamp half of the row
+// A claim after a probe is a compare-and-swap of the stamp half of the row
 // word alone.  During a phase's BFS a row word changes only by claims, and
 // every claim sets the stamp to the phase, so a stamp still equal to the
-// probed one means an unchanged word.  The mate half stays as it is (an
-// end's winner writes -2 there itself, see visit_finish).  Returns the
-// stamp found (the probed one when the claim won).
-template <int S>
-DEV uint32_t visit_settle(const DevGraph &g, int r, Visit &v, uint32_t ph)
-{
-    if (v.kind != 2 && v.kind != 3) return 0;
-    uint32_t want = (uint32_t)(v.w >> 32);
-    if (v.kind == 2) {
-        // adjacency range of the column behind r, fetched alongside the claim
-        const int mate = (int)(uint32_t)v.w;
-        v.adj = make_int2(g.colptr[mate], g.colptr[mate + 1]);
-    }
-    __hip_atomic_compare_exchange_strong(reinterpret_cast<uint32_t *>(g.rw) + 2 * (size_t)r + 1, &want, ph,
-                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED, S);
-    return want;  // the stamp found: the probed one when the exchange happened
-}
+// probed one means an unchanged word.  The mate half stays as it is; an
+// end's winner writes -2 there itself (no one reads it before the next grid
+// barrier), as with the atomic-maximum claims.
 
-// Whether the visit claimed its row; `found` is what visit_settle returned.
-DEV bool visit_won(const Visit &v, uint32_t found, uint32_t ph)
-{
-    if (v.kind == 4) return (uint32_t)(v.w >> 32) != ph;
-    return (v.kind == 2 || v.kind == 3) && found == (uint32_t)(v.w >> 32);
-}
-
+// What a winning claim does (row r reached from column col of root's tree;
+// mate = the row's mate, -1 for an end; `put_lo`: the claim left the mate
+// half to be written).
 template <int S>
-DEV void visit_finish(const DevGraph &g, int col, int root, int r, const Visit &v, bool won, uint32_t ph,
-                      int level, uint32_t flags, bool &newcol, int4 &ne, bool &newend, bool &tried, int colmate)
+DEV void claimed(const DevGraph &g, int col, int root, int r, int mate, int2 adj, bool put_lo, uint32_t ph,
+                 int level, uint32_t flags, bool &newcol, int4 &ne, bool &newend, int colmate)
 {
-    if (!won) return;
-    if (v.kind == 4) tried = true;
-    const int mate = (int)(uint32_t)v.w;  // -1 for an end
-    // The winner writes the low word (which no one reads before the next
-    // grid barrier): an atomic maximum left 0 there, so the mate goes back;
-    // an end gets -2 (below, with one end per root, -2 or -1)
     int32_t *lo = reinterpret_cast<int32_t *>(g.rw) + 2 * (size_t)r;
-    if (v.kind == 4 && mate >= 0) st_i<S>(lo, mate);
-    else if (mate < 0 && !((flags & F_WR) && (flags & F_ENDPOINT))) st_i<S>(lo, -2);
     st_i<S>(&g.pred[r], col);
     if (flags & F_FASTALT) st_i<S>(&g.prow[r], colmate);
     if (mate >= 0) {
-        ne = make_int4(mate, root, v.adj.x, v.adj.y);
+        if (put_lo) st_i<S>(lo, mate);
+        ne = make_int4(mate, root, adj.x, adj.y);
         newcol = true;
         if (flags & F_LEVELS) {
             g.clevel[mate] = level + 1;
             if (g.croot) g.croot[mate] = root;
         }
     } else if ((flags & F_WR) && (flags & F_ENDPOINT)) {
-        // the root's path ends at the first unmatched row it reached; a
-        // later one returns to unmatched (-1), its stamp keeping it out of
-        // this phase
+        // one end per root: the first row reached; a later one returns to
+        // unmatched (-1), its stamp keeping it out of this phase
         newend = __hip_atomic_exchange(&g.cdone[root], ph, __ATOMIC_RELAXED, S) != ph;
         st_i<S>(lo, newend ? -2 : -1);
     } else {
+        st_i<S>(lo, -2);
         newend = true;
         if (flags & F_WR) st_u<S>(&g.cdone[root], ph);
     }
+}
+
+// The claim of a probed row: the stamp found (the probed one when the
+// exchange happened).
+template <int S>
+DEV uint32_t claim_stamp(const DevGraph &g, int r, uint32_t seen, uint32_t ph)
+{
+    __hip_atomic_compare_exchange_strong(reinterpret_cast<uint32_t *>(g.rw) + 2 * (size_t)r + 1, &seen, ph,
+                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED, S);
+    return seen;
 }
 
 template <int S>
 DEV void visit_edge(const DevGraph &g, int col, int root, int r, uint32_t ph, int level, uint32_t flags,
                     bool &newcol, int4 &ne, bool &newend, bool &tried, int colmate)
 {
-    Visit v = visit_issue<S>(g, r, true, ph, flags);
-    visit_decide(v, ph, tried);
-    const uint32_t found = visit_settle<S>(g, r, v, ph);
-    visit_finish<S>(g, col, root, r, v, visit_won(v, found, ph), ph, level, flags, newcol, ne, newend, tried,
-                    colmate);
+    if (flags & F_MAXCLAIM) {
+        // Low-degree rows: one atomic maximum of the phase stamp claims the
+        // row and returns its old word (a row already stamped this phase is
+        // left as it is); the mate's adjacency range comes from radj, loaded
+        // alongside.  Stamps only grow during a run, so exactly one visitor
+        // per phase sees an older stamp.  The maximum leaves 0 in the mate
+        // half: the winner puts the mate back.
+        const int2 adj = g.radj[r];
+        const uint64_t old = __hip_atomic_fetch_max(&g.rw[r], (uint64_t)ph << 32, __ATOMIC_RELAXED, S);
+        if ((uint32_t)(old >> 32) == ph) return;
+        tried = true;
+        claimed<S>(g, col, root, r, (int)(uint32_t)old, adj, true, ph, level, flags, newcol, ne, newend, colmate);
+        return;
+    }
+    // agent scope reads the memory-side copy, which other XCDs' claims
+    // update; a stale L2 copy would send every scanner of a popular row
+    // into a failing compare-and-swap
+    const uint64_t w = (S == kAgent) ? __hip_atomic_load(&g.rw[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : g.rw[r];
+    const uint32_t seen = (uint32_t)(w >> 32);
+    if (seen == ph) return;                           // reached earlier in this phase
+    const int mate = (int)(uint32_t)w;
+    if (mate < -1) return;
+    tried = true;                                     // a compare-and-swap follows
+    // adjacency range of the column behind r, fetched alongside the claim
+    int2 adj = make_int2(0, 0);
+    if (mate >= 0) adj = make_int2(g.colptr[mate], g.colptr[mate + 1]);
+    if (claim_stamp<S>(g, r, seen, ph) == seen)
+        claimed<S>(g, col, root, r, mate, adj, false, ph, level, flags, newcol, ne, newend, colmate);
+}
+
+// Two probed edges per lane (probe claims; wave mapping): the steps of
+// visit_edge taken for both edges at once, each step's two memory accesses
+// in flight together.  The probes go out for every lane, with or without an
+// edge to visit (`on`), so that nothing branches between them, and both
+// are decided before either claim goes out (the wavefront's vote on whether
+// any claim follows needs both), so that no wait for the second probe falls
+// between the claims.
+template <int S>
+DEV void visit_pair(const DevGraph &g, const int r[2], const bool on[2], uint32_t ph, bool claim[2], int mate[2],
+                    int2 adj[2], bool won[2])
+{
+    uint64_t w[2];
+    uint32_t seen[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        w[u] = (S == kAgent) ? __hip_atomic_load(&g.rw[r[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : g.rw[r[u]];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        seen[u] = (uint32_t)(w[u] >> 32);
+        mate[u] = (int)(uint32_t)w[u];
+        claim[u] = on[u] && seen[u] != ph && mate[u] >= -1;
+        won[u] = false;
+    }
+    if (__ballot(claim[0] || claim[1]) == 0) return;  // a round of rows all reached before
+    uint32_t found[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        found[u] = ~seen[u];
+        if (claim[u]) {
+            if (mate[u] >= 0) adj[u] = make_int2(g.colptr[mate[u]], g.colptr[mate[u] + 1]);
+            found[u] = claim_stamp<S>(g, r[u], seen[u], ph);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) won[u] = claim[u] && found[u] == seen[u];
 }
 
 struct LevelIO {
@@ -612,12 +610,7 @@ DEV void expand_entries(const DevGraph &g, const int4 e, const bool have, uint32
             const uint32_t odone = late ? (uint32_t)__shfl((int)rdone, own, 64) : 0u;
             return k < total && (!late || odone != ph);
         };
-        auto finish = [&](int r, int own, const Visit &v, bool won, bool tried) {
-            const int col = __shfl(e.x, own, 64), root = __shfl(e.y, own, 64);
-            const int omate = (flags & F_FASTALT) ? __shfl(cmate, own, 64) : -1;
-            bool newcol = false, newend = false;
-            int4 ne = make_int4(0, 0, 0, 0);
-            visit_finish<S>(g, col, root, r, v, won, ph, level, flags, newcol, ne, newend, tried, omate);
+        auto stage = [&](int r, bool newcol, const int4 &ne, bool newend, bool tried) {
             push_entry(newcol, ne, o.split, st, io.next);
             push_end(newend, r, st, g.ends, io.ecnt, io.next.atomic);
             any_end |= newend;
@@ -629,45 +622,40 @@ DEV void expand_entries(const DevGraph &g, const int4 e, const bool have, uint32
         };
         for (int eb = 0; eb < total;) {
             if (PAIR && !(flags & F_MAXCLAIM) && total - eb > 64) {
-                // Two edges per lane (probe claims): both rows are loaded,
-                // then both probed, then both compared-and-swapped, each
-                // step's two accesses in flight together, so that 128 edges
-                // wait for about as many round trips to memory as 64.  The
-                // probes are plain reads and go out for every lane, with or
-                // without an edge to visit, so that nothing branches between
-                // them.  (The owners are found again after the claims rather
-                // than held in registers through them.)
-                const int k0 = eb + lane, k1 = eb + 64 + lane;
-                int own0 = owner(k0), own1 = owner(k1);
-                const int r0 = row(k0, own0), r1 = row(k1, own1);
-                Visit v0 = visit_issue<S>(g, r0, true, ph, flags);
-                Visit v1 = visit_issue<S>(g, r1, true, ph, flags);
-                if (!live(k0, own0)) v0.kind = 0;
-                if (!live(k1, own1)) v1.kind = 0;
-                // both probes are decided before either claim goes out (the
-                // wavefront's vote on whether any claim follows needs both),
-                // so that no wait for the second probe falls between the
-                // claims; a round of rows all reached before skips them
-                bool t0 = false, t1 = false;
-                visit_decide(v0, ph, t0);
-                visit_decide(v1, ph, t1);
-                uint32_t f0 = 0, f1 = 0;
-                if (__ballot(t0 || t1) != 0) {
-                    f0 = visit_settle<S>(g, r0, v0, ph);
-                    f1 = visit_settle<S>(g, r1, v1, ph);
+                // two edges per lane: 128 edges wait for about as many round
+                // trips to memory as 64 (rows, probes, claims)
+                const int k[2] = {eb + lane, eb + 64 + lane};
+                const int own[2] = {owner(k[0]), owner(k[1])};
+                const int r[2] = {row(k[0], own[0]), row(k[1], own[1])};
+                const bool on[2] = {live(k[0], own[0]), live(k[1], own[1])};
+                bool claim[2], won[2];
+                int mate[2];
+                int2 adj[2] = {make_int2(0, 0), make_int2(0, 0)};
+                visit_pair<S>(g, r, on, ph, claim, mate, adj, won);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int col = __shfl(e.x, own[u], 64), root = __shfl(e.y, own[u], 64);
+                    const int omate = (flags & F_FASTALT) ? __shfl(cmate, own[u], 64) : -1;
+                    bool newcol = false, newend = false;
+                    int4 ne = make_int4(0, 0, 0, 0);
+                    if (won[u])
+                        claimed<S>(g, col, root, r[u], mate[u], adj[u], false, ph, level, flags, newcol, ne, newend,
+                                   omate);
+                    stage(r[u], newcol, ne, newend, claim[u]);
                 }
-                const bool won0 = visit_won(v0, f0, ph), won1 = visit_won(v1, f1, ph);
-                finish(r0, owner(k0), v0, won0, t0);
-                finish(r1, owner(k1), v1, won1, t1);
                 eb += 128;
             } else {
+                // (the owner's column, root and mate are shuffled while the
+                // row is loaded: low-degree graphs run long chains of such
+                // rounds)
                 const int k = eb + lane, own = owner(k);
                 const int r = row(k, own);
-                Visit v = visit_issue<S>(g, r, live(k, own), ph, flags);
-                bool tried = false;
-                visit_decide(v, ph, tried);
-                const uint32_t f = visit_settle<S>(g, r, v, ph);
-                finish(r, own, v, visit_won(v, f, ph), tried);
+                const int col = __shfl(e.x, own, 64), root = __shfl(e.y, own, 64);
+                const int omate = (flags & F_FASTALT) ? __shfl(cmate, own, 64) : -1;
+                bool newcol = false, newend = false, tried = false;
+                int4 ne = make_int4(0, 0, 0, 0);
+                if (live(k, own)) visit_edge<S>(g, col, root, r, ph, level, flags, newcol, ne, newend, tried, omate);
+                stage(r, newcol, ne, newend, tried);
                 eb += 64;
             }
         }
@@ -695,7 +683,11 @@ DEV void expand_entries(const DevGraph &g, const int4 e, const bool have, uint32
 
 // SINGLE: a launch for one graph (mcm_match); the others (batches, the
 // server's multi-graph launch) compile the recorded-row Alternate out.
-template <bool WAVE, int S, bool SINGLE = true>
+// PAIR: the form with two-edge rounds for probe claims (expand_entries),
+// which launches for one graph take unless rows are claimed by atomic
+// maximum: low-degree graphs run long chains of small rounds, and with the
+// two-edge code in their loop they ran 5% slower (grid2048).
+template <bool WAVE, int S, bool SINGLE = true, bool PAIR = false>
 DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
                           int level, const RunOpt &o, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc,
                           uint32_t local = 0)
@@ -720,7 +712,7 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
     const bool dyn = (uint64_t)nwaves * B < n;
     uint32_t *ctr = s_tmp + kBatchCtr;
     auto expand = [&](const int4 e, const bool have) {
-        expand_entries<WAVE, S, SINGLE>(g, e, have, ph, level, flags, late, o, io, st, acc, any_end);
+        expand_entries<WAVE, S, PAIR>(g, e, have, ph, level, flags, late, o, io, st, acc, any_end);
     };
     // one batch of entries [base, base + B) of the frontier
     auto batch = [&](const uint32_t base) {
@@ -1544,7 +1536,10 @@ DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uin
         int4 *cur = (L & 1) ? g.fq1 : g.fq0;
         const LevelIO io{QSink{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], nullptr, (flags & F_DEFER) != 0},
                          &s_loc[4], &s_loc[3], ctrl, false};
-        expand_level<WAVE, kGroup, SINGLE>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
+        if (SINGLE && !(o.flags & F_MAXCLAIM))
+            expand_level<WAVE, kGroup, SINGLE, true>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
+        else
+            expand_level<WAVE, kGroup, SINGLE>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
         ++levels;
         if ((flags & F_APSB) && *(volatile uint32_t *)&s_loc[3]) { stop = 1; break; }
         ++L;
@@ -1666,9 +1661,14 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             if (gr.b < active) {
                 int4 *cur = (L & 1) ? g.fq1 : g.fq0;
                 const LevelIO io{next, line(ctrl, L_NENDS), fd(L % 3), ctrl, defer};
-                share = expand_level<WAVE, kAgent, SINGLE>(g, cur, s.n, wave, active * (blockDim.x >> 6), ph, L, o,
-                                                           io, st, s_tmp, acc,
-                                                           (!SINGLE || (flags & F_LEVELS)) ? 0u : o.local_levels);
+                const uint32_t lw = active * (blockDim.x >> 6);
+                const uint32_t local = (!SINGLE || (flags & F_LEVELS)) ? 0u : o.local_levels;
+                if (SINGLE && !(flags & F_MAXCLAIM))
+                    share = expand_level<WAVE, kAgent, SINGLE, true>(g, cur, s.n, wave, lw, ph, L, o, io, st, s_tmp,
+                                                                     acc, local);
+                else
+                    share = expand_level<WAVE, kAgent, SINGLE>(g, cur, s.n, wave, lw, ph, L, o, io, st, s_tmp, acc,
+                                                               local);
                 if (!(flags & F_APSB)) share &= 0x7fffffffu;
             }
             ++total_levels;
@@ -2029,7 +2029,10 @@ __global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint
                      line(ctrl, L_NENDS), line(ctrl, L_FOUND0 + L % 3), ctrl, false};
     __shared__ uint64_t s_acc[kAccN];
     Acc acc = make_acc(s_acc, stage_tmp(smem));
-    expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
+    if (o.flags & F_MAXCLAIM)
+        expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
+    else
+        expand_level<WAVE, kAgent, true, true>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
     if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
 }
 
