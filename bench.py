@@ -326,7 +326,7 @@ def bench_single(name, steps, warmup, stats=True, copy_gbs=None):
                     "mapping": mcm.get_option("mapping"), "loop": mcm.get_option("loop"),
                     "claim": ("probe", "max")[last["claim"]], "flush": ("atomic", "defer")[last["flush"]],
                     "wr_check": ("early", "late")[last["wr_check"]],
-                    "local_levels": int(mcm.get_option("local_levels")),
+                    "local_levels": int(last["local_levels"]),
                     "alternate": ("classic", "fast")[last["alternate"]]},
            "generate_s": round(t_gen, 2), "_graph": g}
     if st is not None:

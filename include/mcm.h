@@ -423,7 +423,7 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              on graphs with at most 8
  *                                              edges per row on average,
  *                                              classic otherwise
- *   "local_levels" "6" (default) | "0".."16"   levels of mcm_match's
+ *   "local_levels" "auto" (default) | "0".."16" levels of mcm_match's
  *                                              persistent loop (not the
  *                                              multi-graph launch of
  *                                              batches and the server): a
@@ -437,7 +437,10 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              strictly level-synchronous as
  *                                              in Algorithm 1 (BFS trees are
  *                                              then shortest-path trees; the
- *                                              matching is maximum either way)
+ *                                              matching is maximum either
+ *                                              way); auto = 12 with probe
+ *                                              claims, 6 with atomic-maximum
+ *                                              claims
  *   "roots"     "auto" (default) | "list" | "scan"
  *                                              mcm_match's root scan of a
  *                                              phase: every column (scan),
@@ -532,6 +535,7 @@ typedef struct {
     int64_t pass_bytes;      /* per-phase passes under the fixed byte model (stats=1): 4 B and 1/8 B per
                                 column the root scan reads, 8 B per row FixMatching reads */
     int32_t schedule;        /* BFS of mcm_match: 0 = level-synchronous, 1 = level-free */
+    int32_t local_levels;    /* local levels of the device loop's grid levels (0 on other paths) */
 } mcm_stats;
 
 int mcm_last_stats(mcm_stats *out);

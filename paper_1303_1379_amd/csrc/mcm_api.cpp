@@ -291,7 +291,10 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     r.split = (uint32_t)o.split;
     r.level_entries = (uint32_t)o.level_entries;
     r.idle_sleep = (uint32_t)o.idle_sleep;
-    r.local_levels = (uint32_t)o.local_levels;
+    // auto: 12 where rows are probed before their claim (skewed graphs: rmat23
+    // 3.45 against 3.54 ms with 6), 6 with atomic-maximum claims (low-degree
+    // graphs: grid2048 slower with 10 or 16)
+    r.local_levels = o.local_levels >= 0 ? (uint32_t)o.local_levels : ((flags & F_MAXCLAIM) ? 6u : 12u);
     r.take = (uint32_t)std::min(o.take, 64);
     r.keep = (uint32_t)std::max(o.keep, o.take);
     // roots=list: always the list; auto: while the previous phase had at most
@@ -410,7 +413,7 @@ void record_phases(const uint32_t *pairs, uint32_t phases)
 }
 
 void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int loop, uint32_t flags,
-                  double clock_khz)
+                  double clock_khz, uint32_t local_levels)
 {
     std::lock_guard<std::mutex> lk(g_stats_mu);
     mcm_stats s{};
@@ -440,6 +443,7 @@ void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int l
     s.wr_check = (flags & F_WR_LATE) ? 1 : 0;
     s.alternate = (flags & F_FASTALT) ? 1 : 0;
     s.schedule = (flags & F_ASYNC) && loop == 0 ? 1 : 0;
+    s.local_levels = local_levels;
     g_stats = s;
 }
 
@@ -609,7 +613,8 @@ int64_t match_run(const RunBufs &b, const Options &o, uint32_t flags, bool singl
     const int32_t s = (int32_t)*ctrl_line(b.h_ctrl, L_STATUS);
     const int64_t card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(b.h_ctrl, L_CARD));
     const int64_t init_card = (int64_t)*reinterpret_cast<uint64_t *>(ctrl_line(b.h_ctrl, L_INIT_CARD));
-    record_stats(b.h_ctrl, init_card, card, ms, loop, flags, b.info.clock_khz);
+    record_stats(b.h_ctrl, init_card, card, ms, loop, flags, b.info.clock_khz,
+                 loop == 0 ? run_opt(o, flags, ncols, b.info).local_levels : 0u);
     record_phases((flags & F_STATS) && b.h_ptrace ? b.h_ptrace : nullptr, *ctrl_line(b.h_ctrl, L_PHASE));
     if (s != 0) return fail(MCM_EINTERNAL, "device watchdog fired (status %d)", s);
     return card;
@@ -745,8 +750,9 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "auto") g_opt.alternate = 2;
         else return (int)fail(MCM_EINVAL, "alternate must be fast, classic or auto");
     } else if (k == "local_levels") {
-        if (!as_int(0, 16, &x)) return (int)fail(MCM_EINVAL, "local_levels must be in [0, 16]");
-        g_opt.local_levels = (int)x;
+        if (v == "auto") g_opt.local_levels = -1;
+        else if (!as_int(0, 16, &x)) return (int)fail(MCM_EINVAL, "local_levels must be auto or in [0, 16]");
+        else g_opt.local_levels = (int)x;
     } else if (k == "flush") {
         if (v == "atomic") g_opt.flush = 0;
         else if (v == "defer") g_opt.flush = 1;
@@ -844,7 +850,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "take") v = std::to_string(o.take);
     else if (k == "roots") v = o.roots == 0 ? "scan" : (o.roots == 1 ? "list" : "auto");
     else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
-    else if (k == "local_levels") v = std::to_string(o.local_levels);
+    else if (k == "local_levels") v = o.local_levels < 0 ? "auto" : std::to_string(o.local_levels);
     else if (k == "alternate") v = o.alternate == 0 ? "classic" : (o.alternate == 1 ? "fast" : "auto");
     else if (k == "multi_group") v = std::to_string(o.multi_group);
     else if (k == "batch_min") v = std::to_string(o.batch_min);

@@ -89,7 +89,8 @@ struct Options {
     int endpoints = 2;        // WR path ends per root: 0 all reached, 1 the first only, 2 auto (1 for APsB)
     int claim = 2;            // row claim: 0 probe + compare-and-swap, 1 atomic maximum, 2 auto (by degree)
     int flush = 2;            // grid levels: 0 reserve by a queue atomic, 1 through the counter barrier, 2 auto (1)
-    int local_levels = 6;     // grid levels: a wavefront expands its own new entries this many times more
+    int local_levels = -1;    // grid levels: a wavefront expands its own new entries this many times more
+                              // (-1 = auto: 12 with probe claims, 6 with atomic-maximum claims)
     int alternate = 2;        // mcm_match's Alternate: 0 classic, 1 recorded rows, 2 auto (1 on low degree)
     int schedule = 0;         // mcm_match's BFS: 0 level-synchronous, 1 level-free, 2 auto (= 0)
     int fix = 2;              // mcm_match's FixMatching: 0 every row, 1 the rows the walks touched, 2 auto (1 in
@@ -223,7 +224,7 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
 uint32_t base_flags(const Options &o, int64_t nc, int64_t nnz_hint);
 int current_device(int *dev);
 void record_stats(uint32_t *hc, int64_t init_card, int64_t card, float ms, int loop, uint32_t flags,
-                  double clock_khz);
+                  double clock_khz, uint32_t local_levels = 0);
 // The per-phase record of the last stats run of mcm_match (pairs of BFS
 // levels and unmatched rows reached), or none.
 void record_phases(const uint32_t *pairs, uint32_t phases);

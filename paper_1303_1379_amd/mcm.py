@@ -59,7 +59,8 @@ class mcm_stats(ctypes.Structure):
                 ("card", ctypes.c_int64), ("kernel_ms", ctypes.c_double), ("loop", ctypes.c_int32),
                 ("mapping", ctypes.c_int32), ("claims_tried", ctypes.c_int64), ("claim", ctypes.c_int32),
                 ("flush", ctypes.c_int32), ("wr_check", ctypes.c_int32), ("alternate", ctypes.c_int32),
-                ("pass_bytes", ctypes.c_int64), ("schedule", ctypes.c_int32)]
+                ("pass_bytes", ctypes.c_int64), ("schedule", ctypes.c_int32),
+                ("local_levels", ctypes.c_int32)]
 
 
 EXPORTS = ["mcm_match", "mcm_match_noalloc", "mcm_match_batched", "mcm_konig_cover", "mcm_bfs_levels", "mcm_cheap_init_host",

@@ -40,7 +40,7 @@ def test_options_roundtrip_and_rejects():
                  ("level_entries", "0"), ("idle_sleep", "32"), ("wr_check", "early"), ("wr_check", "late"), ("multi_threshold", "0"),
                  ("multi_group", "8"), ("max_blocks", "32"), ("endpoints", "one"), ("barrier", "counter"),
                  ("claim", "max"), ("claim", "probe"), ("flush", "atomic"), ("flush", "defer"),
-                 ("local_levels", "2"), ("alternate", "classic"), ("alternate", "fast"), ("roots", "list"), ("fix", "scan"), ("schedule", "async")]:
+                 ("local_levels", "2"), ("local_levels", "auto"), ("alternate", "classic"), ("alternate", "fast"), ("roots", "list"), ("fix", "scan"), ("schedule", "async")]:
         old = mcm.get_option(k)
         mcm.set_option(k, v)
         assert mcm.get_option(k) == v

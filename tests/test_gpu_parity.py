@@ -35,7 +35,7 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels=6,
+                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels="auto",
                 alternate="auto", schedule="levels", fix="auto", roots="auto")
 
 
@@ -277,10 +277,11 @@ def test_auto_claim_and_flush(name, low):
     barrier."""
     g = gg.workload(name)
     ref = _oracle_card(g)
-    _set(wg_threshold=0)
+    _set(wg_threshold=0, local_levels="auto")
     assert _gpu(g, certify=False)[0] == ref
     s = mcm.last_stats()
     assert (s["claim"], s["flush"], s["wr_check"], s["alternate"]) == ((1, 1, 1, 1) if low else (0, 0, 0, 0))
+    assert s["local_levels"] == (6 if low else 12)
     _set(loop="host")
     assert _gpu(g, certify=False)[0] == ref
     assert mcm.last_stats()["flush"] == 0
