@@ -441,6 +441,14 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              way); auto = 12 with probe
  *                                              claims, 6 with atomic-maximum
  *                                              claims
+ *   "local_edges" "1024" (default) | "0".."1048576"
+ *                                              a local level takes only the
+ *                                              newest staged entries whose
+ *                                              edges add up to at most this
+ *                                              many (at least one entry); the
+ *                                              rest wait for the next grid
+ *                                              level, where every wavefront
+ *                                              shares them; 0 = the newest 64
  *   "roots"     "auto" (default) | "list" | "scan"
  *                                              mcm_match's root scan of a
  *                                              phase: every column (scan),

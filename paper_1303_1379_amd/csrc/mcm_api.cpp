@@ -295,6 +295,7 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     // 3.45 against 3.54 ms with 6), 6 with atomic-maximum claims (low-degree
     // graphs: grid2048 slower with 10 or 16)
     r.local_levels = o.local_levels >= 0 ? (uint32_t)o.local_levels : ((flags & F_MAXCLAIM) ? 6u : 12u);
+    r.local_edges = (uint32_t)o.local_edges;
     r.take = (uint32_t)std::min(o.take, 64);
     r.keep = (uint32_t)std::max(o.keep, o.take);
     // roots=list: always the list; auto: while the previous phase had at most
@@ -749,6 +750,9 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "classic") g_opt.alternate = 0;
         else if (v == "auto") g_opt.alternate = 2;
         else return (int)fail(MCM_EINVAL, "alternate must be fast, classic or auto");
+    } else if (k == "local_edges") {
+        if (!as_int(0, 1 << 20, &x)) return (int)fail(MCM_EINVAL, "local_edges must be in [0, 1048576]");
+        g_opt.local_edges = (int)x;
     } else if (k == "local_levels") {
         if (v == "auto") g_opt.local_levels = -1;
         else if (!as_int(0, 16, &x)) return (int)fail(MCM_EINVAL, "local_levels must be auto or in [0, 16]");
@@ -850,6 +854,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "take") v = std::to_string(o.take);
     else if (k == "roots") v = o.roots == 0 ? "scan" : (o.roots == 1 ? "list" : "auto");
     else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
+    else if (k == "local_edges") v = std::to_string(o.local_edges);
     else if (k == "local_levels") v = o.local_levels < 0 ? "auto" : std::to_string(o.local_levels);
     else if (k == "alternate") v = o.alternate == 0 ? "classic" : (o.alternate == 1 ? "fast" : "auto");
     else if (k == "multi_group") v = std::to_string(o.multi_group);

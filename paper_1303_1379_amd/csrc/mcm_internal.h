@@ -107,6 +107,8 @@ struct RunOpt {
     uint32_t idle_sleep;   // polls of a barrier waiter that did not arrive are this many s_sleep(1) apart
     uint32_t local_levels; // grid levels: times a wavefront expands its own newest entries before the
                            // level ends (0 = strictly level-synchronous)
+    uint32_t local_edges;  // a local level takes the newest entries whose edges add up to at most this many
+                           // (at least one entry; 0 = the newest 64 whatever their edges)
     uint32_t keep;         // level-free BFS: a wavefront keeps at most this many entries (hands older ones on)
     uint32_t take;         // level-free BFS: entries of its own a wavefront expands per step (1..64, <= keep)
     uint32_t roots_max;    // with a root list: a phase scans the previous phase's roots only when there are at

@@ -739,14 +739,28 @@ DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave
         // claimed in the same tree, so the trees stay alternating BFS
         // trees; a column expanded this way is one level early for its tree
         // (levels are then no longer exact, so level-set runs pass 0).
+        // A local level takes only the newest entries whose edges add up to
+        // at most o.local_edges (at least one entry): the rest stay staged
+        // for the next grid level, where every wavefront shares them, rather
+        // than one wavefront scanning a thousand edges while the grid waits.
         for (uint32_t k = 0; k < local; ++k) {
             const int m = st.nq < 64 ? st.nq : 64;
             if (m == 0) break;
             wave_lds_sync();
-            const bool have = lane < m;
-            const int4 e = have ? st.q[st.nq - m + lane] : make_int4(0, 0, 0, 0);
+            const int4 e = lane < m ? st.q[st.nq - m + lane] : make_int4(0, 0, 0, 0);
+            int t = m;
+            if (o.local_edges) {
+                // edges of this entry and every newer one (lanes hold the
+                // newest m in order, the newest last)
+                const int d = lane < m ? e.w - e.z : 0;
+                const int incl = wave_incl_scan(d);
+                const int newer = __shfl(incl, 63, 64) - (incl - d);
+                const uint64_t fit = __ballot(lane < m && (lane == m - 1 || (uint32_t)newer <= o.local_edges));
+                t = __popcll(fit);
+            }
+            const bool have = lane >= m - t && lane < m;
             wave_lds_sync();
-            st.nq -= m;
+            st.nq -= t;
             expand(e, have);
         }
     }

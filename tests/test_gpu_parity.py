@@ -35,7 +35,7 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels="auto",
+                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels="auto", local_edges=1024,
                 alternate="auto", schedule="levels", fix="auto", roots="auto")
 
 
@@ -265,6 +265,22 @@ def test_local_levels(local, combo, name):
     _set(wg_threshold=0, loop="device", small_max=0, local_levels=local, **combo)
     assert _gpu(g)[0] == _oracle_card(g), (local, combo)
     assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (local, combo)
+
+
+# A local level takes only the newest staged entries whose edges fit the
+# local_edges budget (at least one entry), leaving the older ones staged for
+# the next grid level: budgets of one edge (one entry per local level), of a
+# few entries, the default and none; both claims, both drivers.
+@pytest.mark.parametrize("edges", [1, 40, 1024, 0])
+@pytest.mark.parametrize("combo", [dict(driver="apfb", claim="probe"), dict(driver="apsb", claim="max"),
+                                   dict(driver="apfb", claim="max", endpoints="all")],
+                         ids=lambda c: "-".join(str(v) for v in c.values()))
+@pytest.mark.parametrize("name", ["rmat15", "grid256p", "uniform2000"])
+def test_local_edge_budget(edges, combo, name):
+    g = gg.workload(name)
+    _set(wg_threshold=0, loop="device", small_max=0, local_levels=16, local_edges=edges, **combo)
+    assert _gpu(g)[0] == _oracle_card(g), (edges, combo)
+    assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (edges, combo)
 
 
 @pytest.mark.parametrize("name,low", [("grid256p", True), ("uniform2000", True), ("rmat15", False)])
