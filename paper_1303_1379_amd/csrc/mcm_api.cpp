@@ -373,7 +373,7 @@ int64_t run_graph(const RunBufs &b, const Options &o, const DevGraph &g, uint32_
         phases = ph;
         if (ne == 0 || (flags & F_NOAUG)) break;
         HIPCHK(launch_alternate(g, b.ctrl, ne, flags, st));
-        HIPCHK(launch_fix(g, b.ctrl, flags, st));
+        HIPCHK(launch_fix(g, b.ctrl, ph, flags, st));
     }
     if (b.ev1) HIPCHK(hipEventRecord(b.ev1, st));
     // record counts in the device control block so both loops report alike

@@ -26,7 +26,7 @@ hipError_t launch_persistent(const DevGraph &, uint32_t *, uint32_t *, const Run
 hipError_t launch_init_roots(const DevGraph &, uint32_t *, const RunOpt &, hipStream_t);
 hipError_t launch_level(const DevGraph &, uint32_t *, uint32_t, uint32_t, int, const RunOpt &, bool, int, hipStream_t);
 hipError_t launch_alternate(const DevGraph &, uint32_t *, uint32_t, uint32_t, hipStream_t);
-hipError_t launch_fix(const DevGraph &, uint32_t *, uint32_t, hipStream_t);
+hipError_t launch_fix(const DevGraph &, uint32_t *, uint32_t ph, uint32_t flags, hipStream_t);
 hipError_t launch_finish(const DevGraph &, int32_t *, uint32_t *, hipStream_t);
 hipError_t launch_cover(const DevGraph &, uint32_t, uint8_t *, uint8_t *, uint32_t *, hipStream_t);
 hipError_t launch_export_pred(const DevGraph &, uint32_t, int32_t *, hipStream_t);

@@ -1245,8 +1245,13 @@ DEV void fix_listed(const DevGraph &g, uint32_t n, uint32_t tid, uint32_t nthrea
 
 // FixMatching: a row whose column points elsewhere lost a race and is
 // unmatched; a row still marked -2 (its walk stopped before reaching it)
-// returns to -1.  cmatch is not touched.
-DEV void fix_matching(const DevGraph &g, uint32_t tid, uint32_t nthreads, uint32_t flags, Acc &acc)
+// returns to -1.  cmatch is not touched.  Only rows claimed in phase `ph`
+// can be left so: every row a walk writes, stops at or leaves behind (the
+// old mate of a flipped column is the walk's next row) was claimed in the
+// phase, and so was every end marked -2.  The others keep a mate that
+// points back, and their mate's column is not gathered (ph = 0: every
+// matched row is checked).
+DEV void fix_matching(const DevGraph &g, uint32_t ph, uint32_t tid, uint32_t nthreads, uint32_t flags, Acc &acc)
 {
     uint64_t resets = 0;
     int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);
@@ -1254,16 +1259,21 @@ DEV void fix_matching(const DevGraph &g, uint32_t tid, uint32_t nthreads, uint32
     // kStream rows per thread and step: their words, then their columns'
     // mates, loaded together (clamped indices, masked afterwards)
     for (uint32_t r0 = tid; r0 < nr; r0 += nthreads * kStream) {
-        int m[kStream], cm[kStream];
+        uint64_t w[kStream];
+        int cm[kStream];
 #pragma unroll
-        for (int u = 0; u < kStream; ++u) m[u] = rlo[2 * (size_t)min(r0 + u * nthreads, nr - 1)];
+        for (int u = 0; u < kStream; ++u) w[u] = g.rw[min(r0 + u * nthreads, nr - 1)];
 #pragma unroll
-        for (int u = 0; u < kStream; ++u) cm[u] = g.cmatch[m[u] >= 0 ? m[u] : 0];
+        for (int u = 0; u < kStream; ++u) {
+            const int m = (int)(uint32_t)w[u];
+            cm[u] = (m >= 0 && (ph == 0 || (uint32_t)(w[u] >> 32) == ph)) ? g.cmatch[m] : (int)(r0 + u * nthreads);
+        }
 #pragma unroll
         for (int u = 0; u < kStream; ++u) {
             const uint32_t r = r0 + u * nthreads;
-            if (r >= nr || m[u] == -1) continue;
-            if (m[u] < 0 || cm[u] != (int)r) { rlo[2 * (size_t)r] = -1; resets += (m[u] >= 0); }
+            const int m = (int)(uint32_t)w[u];
+            if (r >= nr || m == -1) continue;
+            if (m < 0 || cm[u] != (int)r) { rlo[2 * (size_t)r] = -1; resets += (m >= 0); }
         }
     }
     if (flags & F_STATS) acc.add(S_FIX, resets);
@@ -1717,7 +1727,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             fix_listed(g, ntouch, tid, nthreads, flags, acc);
             if (timing && gr.b == 0) acc.tick(S_PASS, 8ull * ntouch);
         } else {
-            fix_matching(g, tid, nthreads, flags, acc);
+            fix_matching(g, ph, tid, nthreads, flags, acc);
             if (timing && gr.b == 0) acc.tick(S_PASS, 8ull * (uint32_t)g.nr);
         }
         if ((flags & F_DEFER) && left.stop) {
@@ -1774,7 +1784,7 @@ DEV bool run_block(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, Acc &acc,
         if (ne == 0 || (flags & F_NOAUG)) break;
         alternate<kGroup>(g, ne, threadIdx.x, blockDim.x, flags & ~(uint32_t)F_FASTALT, ctrl, acc);
         __syncthreads();
-        fix_matching(g, threadIdx.x, blockDim.x, flags, acc);
+        fix_matching(g, ph, threadIdx.x, blockDim.x, flags, acc);
         if (flags & F_STATS) acc.tick(S_PASS, 8ull * (uint32_t)g.nr);
     }
     __syncthreads();
@@ -2059,11 +2069,11 @@ __global__ void k_alternate(DevGraph g, uint32_t *ctrl, uint32_t flags)
     if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
 }
 
-__global__ void k_fix(DevGraph g, uint32_t *ctrl, uint32_t flags)
+__global__ void k_fix(DevGraph g, uint32_t *ctrl, uint32_t ph, uint32_t flags)
 {
     __shared__ uint64_t s_acc[kAccN];
     Acc acc = make_acc(s_acc);
-    fix_matching(g, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, flags, acc);
+    fix_matching(g, ph, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, flags, acc);
     if ((flags & F_STATS) && blockIdx.x == 0) acc.tick(S_PASS, 8ull * (uint32_t)g.nr);
     if (flags & F_STATS) acc.flush(reinterpret_cast<uint64_t *>(line(ctrl, L_STAT0)), false);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -2332,9 +2342,9 @@ hipError_t launch_alternate(const DevGraph &g, uint32_t *ctrl, uint32_t nends, u
     return hipGetLastError();
 }
 
-hipError_t launch_fix(const DevGraph &g, uint32_t *ctrl, uint32_t flags, hipStream_t st)
+hipError_t launch_fix(const DevGraph &g, uint32_t *ctrl, uint32_t ph, uint32_t flags, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fix, dim3(clamp_blocks(g.nr, 256, 1, 4096)), dim3(256), 0, st, g, ctrl, flags);
+    hipLaunchKernelGGL(k_fix, dim3(clamp_blocks(g.nr, 256, 1, 4096)), dim3(256), 0, st, g, ctrl, ph, flags);
     return hipGetLastError();
 }
 
