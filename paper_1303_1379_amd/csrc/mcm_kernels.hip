@@ -1804,24 +1804,47 @@ __global__ void k_setup(DevGraph g, const int32_t *init_c, const int32_t *init_r
 {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nt = gridDim.x * blockDim.x;
+    const uint32_t nc = (uint32_t)g.nc, nr = (uint32_t)g.nr;
     uint64_t m0 = 0;
-    for (uint32_t c = tid; c < (uint32_t)g.nc; c += nt) {
-        const int r = init_c ? init_c[c] : -1;
-        g.cmatch[c] = r;
-        m0 += r >= 0;
-        g.cdone[c] = 0;
-        if (flags & F_LEVELS) {
-            g.clevel[c] = -1;
-            if (g.croot) g.croot[c] = -1;
+    // kStream elements per thread and step, their loads issued together
+    // (indices clamped, stores masked)
+    for (uint32_t c0 = tid; c0 < nc; c0 += nt * kStream) {
+        int r[kStream];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) r[u] = init_c ? init_c[min(c0 + u * nt, nc - 1)] : -1;
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) {
+            const uint32_t c = c0 + u * nt;
+            if (c >= nc) continue;
+            g.cmatch[c] = r[u];
+            m0 += r[u] >= 0;
+            g.cdone[c] = 0;
+            if (flags & F_LEVELS) {
+                g.clevel[c] = -1;
+                if (g.croot) g.croot[c] = -1;
+            }
         }
     }
     if (flags & (F_DEFER | F_ASYNC))
         for (uint64_t i = tid; i < 2 * g.qcap; i += nt) g.fq0[i] = make_int4(-1, -1, -1, -1);
-    for (uint32_t r = tid; r < (uint32_t)g.nr; r += nt) {
-        const int m = init_r ? init_r[r] : -1;
-        g.rw[r] = (uint64_t)(uint32_t)m;
-        if (flags & F_LEVELS) g.pred[r] = -1;
-        if (flags & F_MAXCLAIM) g.radj[r] = m >= 0 ? make_int2(g.colptr[m], g.colptr[m + 1]) : make_int2(0, 0);
+    for (uint32_t r0 = tid; r0 < nr; r0 += nt * kStream) {
+        int m[kStream];
+        int2 adj[kStream];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) m[u] = init_r ? init_r[min(r0 + u * nt, nr - 1)] : -1;
+        if (flags & F_MAXCLAIM) {
+#pragma unroll
+            for (int u = 0; u < kStream; ++u)
+                adj[u] = m[u] >= 0 ? make_int2(g.colptr[m[u]], g.colptr[m[u] + 1]) : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) {
+            const uint32_t r = r0 + u * nt;
+            if (r >= nr) continue;
+            g.rw[r] = (uint64_t)(uint32_t)m[u];
+            if (flags & F_LEVELS) g.pred[r] = -1;
+            if (flags & F_MAXCLAIM) g.radj[r] = adj[u];
+        }
     }
     if (bar)
         for (uint32_t i = tid; i < (uint32_t)(kMaxGridBlocks * kLineWords); i += nt) bar[i] = 0;
@@ -2087,9 +2110,24 @@ __global__ void k_finish(DevGraph g, int32_t *out_r, uint32_t *ctrl)
 {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nt = gridDim.x * blockDim.x;
-    for (uint32_t r = tid; r < (uint32_t)g.nr; r += nt) out_r[r] = (int32_t)(uint32_t)g.rw[r];
+    const uint32_t nc = (uint32_t)g.nc, nr = (uint32_t)g.nr;
+    // kStream elements per thread and step, their loads issued together
+    for (uint32_t r0 = tid; r0 < nr; r0 += nt * kStream) {
+        uint64_t w[kStream];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) w[u] = g.rw[min(r0 + u * nt, nr - 1)];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u)
+            if (r0 + u * nt < nr) out_r[r0 + u * nt] = (int32_t)(uint32_t)w[u];
+    }
     uint64_t m = 0;
-    for (uint32_t c = tid; c < (uint32_t)g.nc; c += nt) m += (g.cmatch[c] >= 0);
+    for (uint32_t c0 = tid; c0 < nc; c0 += nt * kStream) {
+        int cm[kStream];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) cm[u] = g.cmatch[min(c0 + u * nt, nc - 1)];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) m += (c0 + u * nt < nc && cm[u] >= 0);
+    }
     block_add(m, reinterpret_cast<uint64_t *>(line(ctrl, L_CARD)));
 }
 
