@@ -484,6 +484,15 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *   "stats"     "0" (default) | "1"            count scanned edges etc.
  *   "tuning"    path of an autotuner cache file (JSON lines) or ""
  *   "autotune"  "0" (default) | "1"            batch plans time candidates
+ *   "wg_lds"    "on" (default) | "off"         mcm_match's one-workgroup path
+ *                                              (graphs with ncols + nrows at
+ *                                              most wg_threshold) keeps the
+ *                                              pattern, row words and
+ *                                              per-vertex state in the
+ *                                              workgroup's LDS when they fit
+ *                                              there (4 (ncols + 1) + 4 nnz +
+ *                                              12 nrows + 8 ncols bytes, up to
+ *                                              what the LDS staging leaves)
  *   "block", "blocks_per_cu", "wg_block", "wg_threshold", "small_max",
  *   "batch_min", "split", "timeout_s", "max_blocks", "level_entries",
  *   "idle_sleep", "barrier", "multi_threshold", "multi_group"

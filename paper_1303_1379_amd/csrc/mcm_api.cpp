@@ -128,6 +128,7 @@ int64_t get_device_info(int dev, DevInfo *info)
     HIPCHK(hipGetDeviceProperties(&prop, dev));
     info->ncu = prop.multiProcessorCount;
     info->arch = prop.gcnArchName;
+    info->lds_block = (int)prop.sharedMemPerBlock;
     int rate = 0;
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate > 0)
         info->clock_khz = rate;
@@ -488,13 +489,16 @@ int64_t run_single_wg(const RunBufs &b, const Options &o, int32_t nc, int32_t nr
     d.fq = b.fq;
     d.ends = b.ends;
     *b.h_desc = d;
-    HIPCHK(prepare_match_wg(o.wg_block));
+    // the rest of the workgroup's LDS holds the graph when it fits (a
+    // kilobyte is left for the kernel's static LDS)
+    const int arena = o.wg_lds ? std::max(0, (b.info.lds_block - stage_lds_bytes(o.wg_block / 64) - 1024) & ~255) : 0;
+    HIPCHK(prepare_match_wg(o.wg_block, arena));
     HIPCHK(hipMemcpyAsync(b.desc, b.h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
     HIPCHK(launch_zero_ctrl(b.ctrl, st));
     RunOpt ro = run_opt(o, flags, nc, b.info);
     ro.split = 0;  // the graph's queue slices hold exactly nc entries
     if (b.ev0) HIPCHK(hipEventRecord(b.ev0, st));
-    HIPCHK(launch_match_wg(b.desc, nullptr, 1, b.card, b.ctrl, ro, (flags & F_WAVE) != 0, 1, o.wg_block, st));
+    HIPCHK(launch_match_wg(b.desc, nullptr, 1, b.card, b.ctrl, ro, (flags & F_WAVE) != 0, 1, o.wg_block, st, arena));
     if (b.ev1) HIPCHK(hipEventRecord(b.ev1, st));
     HIPCHK(hipMemcpyAsync(b.h_ctrl, b.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -750,6 +754,10 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "classic") g_opt.alternate = 0;
         else if (v == "auto") g_opt.alternate = 2;
         else return (int)fail(MCM_EINVAL, "alternate must be fast, classic or auto");
+    } else if (k == "wg_lds") {
+        if (v == "off") g_opt.wg_lds = false;
+        else if (v == "on") g_opt.wg_lds = true;
+        else return (int)fail(MCM_EINVAL, "wg_lds must be on or off");
     } else if (k == "local_edges") {
         if (!as_int(0, 1 << 20, &x)) return (int)fail(MCM_EINVAL, "local_edges must be in [0, 1048576]");
         g_opt.local_edges = (int)x;
@@ -855,6 +863,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "roots") v = o.roots == 0 ? "scan" : (o.roots == 1 ? "list" : "auto");
     else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
     else if (k == "local_edges") v = std::to_string(o.local_edges);
+    else if (k == "wg_lds") v = o.wg_lds ? "on" : "off";
     else if (k == "local_levels") v = o.local_levels < 0 ? "auto" : std::to_string(o.local_levels);
     else if (k == "alternate") v = o.alternate == 0 ? "classic" : (o.alternate == 1 ? "fast" : "auto");
     else if (k == "multi_group") v = std::to_string(o.multi_group);

@@ -30,9 +30,11 @@ hipError_t launch_fix(const DevGraph &, uint32_t *, uint32_t ph, uint32_t flags,
 hipError_t launch_finish(const DevGraph &, int32_t *, uint32_t *, hipStream_t);
 hipError_t launch_cover(const DevGraph &, uint32_t, uint8_t *, uint8_t *, uint32_t *, hipStream_t);
 hipError_t launch_export_pred(const DevGraph &, uint32_t, int32_t *, hipStream_t);
+// `arena`: bytes of LDS per workgroup for graphs matched in LDS (0 = none)
 hipError_t launch_match_wg(const BatchDesc *descs, const int32_t *order, int32_t ngraphs, int64_t *card,
-                           uint32_t *ctrl, const RunOpt &o, bool wave, int blocks, int block, hipStream_t st);
-hipError_t prepare_match_wg(int block);
+                           uint32_t *ctrl, const RunOpt &o, bool wave, int blocks, int block, hipStream_t st,
+                           int arena = 0);
+hipError_t prepare_match_wg(int block, int arena = 0);
 hipError_t match_wg_occupancy(bool wave, int block, int *per_cu);
 hipError_t launch_cheap_init(const BatchDesc *descs, int32_t ngraphs, hipStream_t st);
 hipError_t multi_occupancy(bool wave, int block, int *per_cu);
@@ -111,6 +113,7 @@ struct Options {
     int max_blocks = 0;       // cap on persistent blocks (0 = one set per CU)
     int wg_block = 1024;      // one-workgroup matcher block size
     int64_t wg_threshold = 16384;  // nc + nr at or below which one workgroup matches alone
+    bool wg_lds = true;       // mcm_match's one-workgroup path keeps a graph that fits in the workgroup's LDS
     int64_t small_max = 256;  // frontiers up to this size are expanded by one workgroup
     int batch_min = 8;        // fewest frontier entries per wavefront batch
     int split = 64;           // heavier columns enter the frontier in pieces of this many edges (0 = off)
@@ -126,6 +129,7 @@ Options opts();
 // ---- per-device workspace (grow-only, one per device, guarded by workspace_mutex)
 struct DevInfo {
     int ncu = 0;
+    int lds_block = 65536;  // bytes of LDS a workgroup may use
     double clock_khz = 100000.0;
     std::string arch;
 };

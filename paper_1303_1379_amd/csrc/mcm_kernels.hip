@@ -2170,9 +2170,22 @@ __global__ void k_zero_ctrl(uint32_t *ctrl)
 // One workgroup per graph.  Used for small single graphs and for batches;
 // blocks take graphs from a queue (ordered largest first by the host) until
 // it is empty.  Every graph gets its own state slices; counters live in LDS.
+// The LDS arena of the one-workgroup kernel: a graph whose pattern and
+// randomly accessed state fit in `arena` bytes is matched there (colptr,
+// rowind, row words, pred, cdone and cmatch in LDS; frontier queues and
+// ends stay in global memory, which they reach in staged, coalesced
+// batches).  The kernel's code reaches LDS and global memory through the
+// same pointers (flat addressing), so the matching steps are the same code.
+DEV size_t lds_al(size_t b) { return (b + 15) & ~(size_t)15; }
+DEV size_t lds_graph_bytes(int32_t nc, int32_t nr, int64_t nnz)
+{
+    return lds_al(4 * ((size_t)nc + 1)) + lds_al(4 * (size_t)nnz) + lds_al(8 * (size_t)nr) + lds_al(4 * (size_t)nr) +
+           2 * lds_al(4 * (size_t)nc);
+}
+
 template <bool WAVE>
 __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const int32_t *order, int32_t ngraphs,
-                                                   int64_t *card, uint32_t *ctrl, RunOpt o)
+                                                   int64_t *card, uint32_t *ctrl, RunOpt o, uint32_t arena)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_loc[16];  // [0..7] level counters, [8..13] barrier state
@@ -2205,6 +2218,26 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
         g.fq1 = d.fq + d.nc;
         g.ends = d.ends;
         g.clevel = nullptr;
+        const int64_t nnz = (arena && g.nc > 0 && g.nr > 0) ? (int64_t)d.colptr[g.nc] : -1;
+        const bool in_lds = nnz >= 0 && lds_graph_bytes(g.nc, g.nr, nnz) <= arena;
+        if (in_lds) {
+            char *a = smem + stage_lds_bytes(blockDim.x >> 6);
+            int32_t *lcp = reinterpret_cast<int32_t *>(a);
+            a += lds_al(4 * ((size_t)g.nc + 1));
+            int32_t *lri = reinterpret_cast<int32_t *>(a);
+            a += lds_al(4 * (size_t)nnz);
+            g.rw = reinterpret_cast<uint64_t *>(a);
+            a += lds_al(8 * (size_t)g.nr);
+            g.pred = reinterpret_cast<int32_t *>(a);
+            a += lds_al(4 * (size_t)g.nr);
+            g.cdone = reinterpret_cast<uint32_t *>(a);
+            a += lds_al(4 * (size_t)g.nc);
+            g.cmatch = reinterpret_cast<int32_t *>(a);
+            for (int c = threadIdx.x; c <= g.nc; c += blockDim.x) lcp[c] = d.colptr[c];
+            for (int64_t i = threadIdx.x; i < nnz; i += blockDim.x) lri[i] = d.rowind[i];
+            g.colptr = lcp;
+            g.rowind = lri;
+        }
         if (threadIdx.x == 0) s_m = 0;
         __syncthreads();
         uint32_t m0 = 0;
@@ -2228,7 +2261,10 @@ __global__ void __launch_bounds__(1024) k_match_wg(const BatchDesc *descs, const
         __syncthreads();
         uint32_t m = 0;
         for (int r = threadIdx.x; r < g.nr; r += blockDim.x) d.out_r[r] = (int32_t)(uint32_t)g.rw[r];
-        for (int c = threadIdx.x; c < g.nc; c += blockDim.x) m += (g.cmatch[c] >= 0);
+        for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+            if (in_lds) d.out_c[c] = g.cmatch[c];
+            m += (g.cmatch[c] >= 0);
+        }
         if (m) atomicAdd(&s_m, m);
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -2407,21 +2443,23 @@ hipError_t launch_export_pred(const DevGraph &g, uint32_t ph, int32_t *row_pred,
 }
 
 hipError_t launch_match_wg(const BatchDesc *descs, const int32_t *order, int32_t ngraphs, int64_t *card,
-                           uint32_t *ctrl, const RunOpt &o, bool wave, int blocks, int block, hipStream_t st)
+                           uint32_t *ctrl, const RunOpt &o, bool wave, int blocks, int block, hipStream_t st, int arena)
 {
-    const int lds = stage_lds_bytes(block / 64);
+    const int lds = stage_lds_bytes(block / 64) + arena;
     if (wave)
-        hipLaunchKernelGGL(k_match_wg<true>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, card, ctrl, o);
+        hipLaunchKernelGGL(k_match_wg<true>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, card, ctrl, o,
+                           (uint32_t)arena);
     else
-        hipLaunchKernelGGL(k_match_wg<false>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, card, ctrl, o);
+        hipLaunchKernelGGL(k_match_wg<false>, dim3(blocks), dim3(block), lds, st, descs, order, ngraphs, card, ctrl, o,
+                           (uint32_t)arena);
     return hipGetLastError();
 }
 
 // Raise the dynamic-LDS limit of the one-workgroup kernel (outside any
 // stream capture).
-hipError_t prepare_match_wg(int block)
+hipError_t prepare_match_wg(int block, int arena)
 {
-    const int lds = stage_lds_bytes(block / 64);
+    const int lds = stage_lds_bytes(block / 64) + arena;
     hipError_t e = allow_lds(reinterpret_cast<const void *>(&k_match_wg<true>), lds);
     if (e != hipSuccess) return e;
     return allow_lds(reinterpret_cast<const void *>(&k_match_wg<false>), lds);

@@ -35,7 +35,7 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels="auto", local_edges=1024,
+                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels="auto", local_edges=1024, wg_lds="on",
                 alternate="auto", schedule="levels", fix="auto", roots="auto")
 
 
@@ -350,6 +350,26 @@ def test_listed_passes(fix, roots, form, name):
     _set(wg_threshold=0, fix=fix, roots=roots, **form)
     assert _gpu(g)[0] == _oracle_card(g), (fix, roots, form)
     assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (fix, roots, form)
+
+
+# The one-workgroup path (ncols + nrows at most wg_threshold) with the graph
+# in the workgroup's LDS where it fits (uniform2000, grid32, the small
+# R-MAT) and in global memory where it does not (rmat13's 110 k edges), and
+# with the arena off; both drivers, both mappings, runs in a row on one
+# workspace, from the greedy and from the empty matching.
+@pytest.mark.parametrize("lds", ["on", "off"])
+@pytest.mark.parametrize("combo", [dict(driver="apfb", mapping="wave"), dict(driver="apsb", mapping="wave"),
+                                   dict(driver="apfb", mapping="thread", endpoints="one")],
+                         ids=lambda c: "-".join(str(v) for v in c.values()))
+@pytest.mark.parametrize("name", ["uniform2000", "grid32", "rmat10", "rmat13"])
+def test_one_workgroup_lds(lds, combo, name):
+    g = gg.workload(name)
+    ref = _oracle_card(g)
+    _set(wg_lds=lds, **combo)
+    assert g.nc + g.nr <= 16384
+    for _ in range(2):
+        assert _gpu(g)[0] == ref, (lds, combo)
+    assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (lds, combo)
 
 
 def test_deferred_levels_repeated():
