@@ -1637,10 +1637,12 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
     const Pub none{0, 0, 0, nullptr, nullptr, false};
     for (;; ++ph) {
         if (ph > o.max_phases) { if (leader) set_status(ctrl, kEInternal); return false; }
-        // every block read the previous phase's count before that phase's
-        // last grid barrier; the walks of this phase report after two more
-        if (leader) *line(ctrl, L_NTOUCH) = 0;
         const uint32_t lv0 = total_levels;
+        // every block read the previous phase's count of reported rows before
+        // the barrier that ends this phase's root scan; the walks of this
+        // phase report after it (an agent-scope store: the barriers between
+        // deferred grid levels carry no release)
+        auto reset_touch = [&]() { if (leader) st_u<kAgent>(line(ctrl, L_NTOUCH), 0u); };
         if (SINGLE && (flags & F_ASYNC)) {
             // level-free phase: roots reserved in the phase-long queue, one
             // grid barrier, then every wavefront works until the queue's
@@ -1649,6 +1651,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
                                                 reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)), ph, ctrl);
             if (!sync_all(none)) return false;
             if (act && leader) mark_active_phase(ctrl, ph);
+            reset_touch();
             async_bfs<WAVE>(g, ctrl, o, ph, nwaves, st, acc);
             ++total_levels;
             if (!sync_all(none)) return false;
@@ -1657,6 +1660,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         const bool act = init_roots<SINGLE>(g, wave, nwaves, o, fc(0), st, s_tmp, acc, nullptr, ph, ctrl);
         if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
         if (act && leader) mark_active_phase(ctrl, ph);
+        reset_touch();
         for (;;) {
             const int L = (int)s.L;
             if (s.n == 0 || s.stop) break;
@@ -1712,6 +1716,15 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         }
         if (ne == 0 || (flags & F_NOAUG)) break;
         const uint64_t ta = timing ? wall_clock64() : 0;
+        if (leader) {
+            // the level loop is over (no block adds to these any more) and the
+            // next root scan starts after Alternate's grid barrier
+            for (int i = 0; i < 3; ++i) { *fc(i) = 0; *fd(i) = 0; }
+            *reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)) = 0;
+            *line(ctrl, L_AQ_TAKE) = 0;
+            // the next phase lists its roots in the half this phase read
+            *line(ctrl, ((ph + 1) & 1) ? L_NRL1 : L_NRL0) = 0;
+        }
         // the walks report the rows they touch when the phase found few ends
         // (o.fix_max); FixMatching then visits only those
         const bool listed = SINGLE && g.touched && ne <= o.fix_max;
@@ -1720,6 +1733,9 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         else
             alternate<kAgent>(g, ne, tid, nthreads, SINGLE ? flags : (flags & ~(uint32_t)F_FASTALT), ctrl, acc);
         if (!sync_all(none)) return false;
+        // every block read the count of ends before this barrier; the next
+        // phase's BFS adds to it after the barrier that ends its root scan
+        if (leader) *line(ctrl, L_NENDS) = 0;
         // FixMatching over the rows the walks touched, unless more were
         // reported than the list holds (then over every row)
         const uint32_t ntouch = listed ? ld_u<kAgent>(line(ctrl, L_NTOUCH)) : 0xffffffffu;
@@ -1730,19 +1746,17 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             fix_matching(g, ph, tid, nthreads, flags, acc);
             if (timing && gr.b == 0) acc.tick(S_PASS, 8ull * (uint32_t)g.nr);
         }
+        // No grid barrier between FixMatching and the next root scan: the
+        // scan reads cmatch, colptr and the root list, which FixMatching does
+        // not write, and the BFS that reads the row words FixMatching writes
+        // starts after the scan's own barrier.  The unread frontier of an
+        // APsB stop is the exception: its slots are set back to -1 here, and
+        // the scan may write the same queue.
         if ((flags & F_DEFER) && left.stop) {
             const QSink lq{(left.L & 1) ? g.fq1 : g.fq0, nullptr, nullptr, true};
             for (uint32_t i = tid; i < left.n; i += nthreads) put_entry(lq, i, make_int4(-1, -1, -1, -1));
+            if (!sync_all(none)) return false;
         }
-        if (leader) {
-            for (int i = 0; i < 3; ++i) { *fc(i) = 0; *fd(i) = 0; }
-            *line(ctrl, L_NENDS) = 0;
-            *reinterpret_cast<uint64_t *>(line(ctrl, L_AQ)) = 0;
-            *line(ctrl, L_AQ_TAKE) = 0;
-            // the next phase lists its roots in the half this phase read
-            *line(ctrl, ((ph + 1) & 1) ? L_NRL1 : L_NRL0) = 0;
-        }
-        if (!sync_all(none)) return false;
         if (timing) acc.tick(S_T_AUGMENT, wall_clock64() - ta);
     }
     if (leader) { *ph_out = ph; *lv_out = total_levels; }
