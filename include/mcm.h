@@ -484,6 +484,12 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *   "stats"     "0" (default) | "1"            count scanned edges etc.
  *   "tuning"    path of an autotuner cache file (JSON lines) or ""
  *   "autotune"  "0" (default) | "1"            batch plans time candidates
+ *   "fuse"      "on" (default) | "off"         mcm_match with probe claims: a
+ *                                              phase that does not list its
+ *                                              roots expands them (BFS level
+ *                                              0) as its root scan finds
+ *                                              them, instead of enqueueing
+ *                                              them for a level of their own
  *   "wg_lds"    "on" (default) | "off"         mcm_match's one-workgroup path
  *                                              (graphs with ncols + nrows at
  *                                              most wg_threshold) keeps the

@@ -533,6 +533,10 @@ uint32_t match_flags(const Options &o, int32_t nc, int32_t nr, int64_t nnz, bool
     // and store per claim cost more than their short walks save, and without
     // WR (many ends per tree) walks would repeat their shared ways.
     if (!single_wg && (o.alternate == 1 || (o.alternate == 2 && low_degree && o.wr))) flags |= F_FASTALT;
+    // Level 0 in the root scan's pass where rows are probed before their
+    // claim (the two-edge rounds; deferred levels keep their checked queue
+    // protocol, and the level-free schedule has no level 0)
+    if (!single_wg && o.fuse && !(flags & (F_MAXCLAIM | F_DEFER))) flags |= F_FUSE0;
     // Level-free BFS (APFB on the device loop only, on request: measured
     // slower than the level loop on grid2048 by 14x): no grid barrier
     // between BFS levels; the deferred level forms do not apply then.
@@ -754,6 +758,10 @@ int mcm_set_option(const char *key, const char *value)
         else if (v == "classic") g_opt.alternate = 0;
         else if (v == "auto") g_opt.alternate = 2;
         else return (int)fail(MCM_EINVAL, "alternate must be fast, classic or auto");
+    } else if (k == "fuse") {
+        if (v == "off") g_opt.fuse = false;
+        else if (v == "on") g_opt.fuse = true;
+        else return (int)fail(MCM_EINVAL, "fuse must be on or off");
     } else if (k == "wg_lds") {
         if (v == "off") g_opt.wg_lds = false;
         else if (v == "on") g_opt.wg_lds = true;
@@ -864,6 +872,7 @@ int mcm_get_option(const char *key, char *buf, int32_t len)
     else if (k == "flush") v = o.flush == 0 ? "atomic" : (o.flush == 1 ? "defer" : "auto");
     else if (k == "local_edges") v = std::to_string(o.local_edges);
     else if (k == "wg_lds") v = o.wg_lds ? "on" : "off";
+    else if (k == "fuse") v = o.fuse ? "on" : "off";
     else if (k == "local_levels") v = o.local_levels < 0 ? "auto" : std::to_string(o.local_levels);
     else if (k == "alternate") v = o.alternate == 0 ? "classic" : (o.alternate == 1 ? "fast" : "auto");
     else if (k == "multi_group") v = std::to_string(o.multi_group);

@@ -113,6 +113,8 @@ struct Options {
     int max_blocks = 0;       // cap on persistent blocks (0 = one set per CU)
     int wg_block = 1024;      // one-workgroup matcher block size
     int64_t wg_threshold = 16384;  // nc + nr at or below which one workgroup matches alone
+    bool fuse = true;         // mcm_match, probe claims: BFS level 0 in the root scan's pass (phases that do not
+                              // list their roots)
     bool wg_lds = true;       // mcm_match's one-workgroup path keeps a graph that fits in the workgroup's LDS
     int64_t small_max = 256;  // frontiers up to this size are expanded by one workgroup
     int batch_min = 8;        // fewest frontier entries per wavefront batch

@@ -62,9 +62,11 @@ enum Flags : uint32_t {
                           // needs F_BAR_COUNTER and qcap
     F_FASTALT = 2048u,    // claims record the row behind the claiming column; Alternate follows it
                           // (two independent loads per step); needs prow
-    F_ASYNC = 4096u       // APFB: a phase's BFS without levels (one phase-long queue that every
+    F_ASYNC = 4096u,      // APFB: a phase's BFS without levels (one phase-long queue that every
                           // wavefront takes entries from as they appear); needs qcap, excludes
                           // F_APSB and F_LEVELS
+    F_FUSE0 = 8192u       // probe claims, launch for one graph: a phase that does not list its roots
+                          // expands them as the root scan finds them (BFS level 0 in the scan's pass)
 };
 
 // Device view of one graph plus its working state.

@@ -687,13 +687,20 @@ DEV void expand_entries(const DevGraph &g, const int4 e, const bool have, uint32
 // which launches for one graph take unless rows are claimed by atomic
 // maximum: low-degree graphs run long chains of small rounds, and with the
 // two-edge code in their loop they ran 5% slower (grid2048).
+// The forms the two-edge level code leaves out (its callers take it only
+// without them): atomic-maximum claims, recorded rows, the root test beside
+// the edge visit, level records, deferred and level-free levels.  Without
+// their registers the level loop fits a 1024-thread workgroup's 128.
+constexpr uint32_t kPairOff = F_MAXCLAIM | F_FASTALT | F_WR_LATE | F_LEVELS | F_DEFER | F_ASYNC;
+DEV bool pair_form(uint32_t flags) { return (flags & kPairOff) == 0; }
+
 template <bool WAVE, int S, bool SINGLE = true, bool PAIR = false>
 DEV uint32_t expand_level(const DevGraph &g, int4 *fq, uint32_t n, uint32_t wave, uint32_t nwaves, uint32_t ph,
                           int level, const RunOpt &o, const LevelIO &io, Stage &st, uint32_t *s_tmp, Acc &acc,
                           uint32_t local = 0)
 {
     const int lane = __lane_id();
-    const uint32_t flags = SINGLE ? o.flags : (o.flags & ~(uint32_t)F_FASTALT);
+    const uint32_t flags = PAIR ? (o.flags & ~kPairOff) : SINGLE ? o.flags : (o.flags & ~(uint32_t)F_FASTALT);
     const uint64_t t0 = (flags & F_STATS) ? wall_clock64() : 0;
     bool any_end = false;
     const uint32_t B = batch_size(n, nwaves, o.batch_min);
@@ -1072,6 +1079,99 @@ DEV bool init_roots(const DevGraph &g, uint32_t wave, uint32_t nwaves, const Run
     st.dq = st.de = 0;
     __syncthreads();
     return active;
+}
+
+// Whether phase ph lists its roots (the previous phase had at most
+// o.roots_max of them; phase 1: the initial matching leaves at most that many
+// columns unmatched).  Every block reads the same counts.
+DEV bool roots_listed(const DevGraph &g, const RunOpt &o, uint32_t ph, uint32_t *ctrl)
+{
+    if (!g.rlist) return false;
+    if (ph > 1) return (ld_u<kAgent>(line(ctrl, ((ph - 1) & 1) ? L_NRL1 : L_NRL0)) & 0x7fffffffu) <= o.roots_max;
+    const uint64_t m0 = __hip_atomic_load(reinterpret_cast<uint64_t *>(line(ctrl, L_INIT_CARD)), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    return (uint64_t)g.nc - m0 <= (uint64_t)o.roots_max;
+}
+
+// LDS of the persistent kernel: the wavefront stages, and kRootQ root
+// entries per wavefront for roots_level0 (up to 63 left from a step plus one
+// step's 64 kStream columns).
+constexpr int kRootQ = 64 * (kStream + 1);
+inline constexpr int persistent_lds_bytes(int waves) { return stage_lds_bytes(waves) + waves * kRootQ * 16; }
+
+// The root scan and BFS level 0 in one pass (F_FUSE0; a phase that does not
+// list its roots): a wavefront gathers the roots of its columns (unmatched
+// columns with edges) in LDS, 64 at a time, and expands them as a level-0
+// frontier batch at once, instead of writing them to the frontier queue for
+// a level that reads them back after one more grid barrier.  Level 1's
+// entries go to fq1, as level 0's would.  Every wavefront still expands
+// every root before the barrier that ends the pass, so the level sets are
+// those of level 0.  Returns the workgroup's share for that barrier: the
+// entries it added to level 1 (low 31 bits) and whether it reached an
+// unmatched row (bit 31).  Counts the phase's roots into its root-list
+// count (one addition per workgroup).
+template <bool WAVE, bool PAIR>
+DEV uint32_t roots_level0(const DevGraph &g, uint32_t wave, uint32_t nwaves, const RunOpt &o, uint32_t ph,
+                          uint32_t *ctrl, Stage &st, uint32_t *s_tmp, Acc &acc)
+{
+    constexpr int kRootCnt = 53;  // s_tmp word: the workgroup's roots
+    const int lane = __lane_id();
+    const uint32_t flags = PAIR ? (o.flags & ~kPairOff) : o.flags;
+    const uint32_t nc = (uint32_t)g.nc;
+    const QSink next{g.fq1, line(ctrl, L_FCOUNT1), nullptr, false};
+    const LevelIO io{next, line(ctrl, L_NENDS), line(ctrl, L_FOUND0), ctrl, false};
+    const bool late = WAVE && (flags & F_WR) && (flags & F_WR_LATE);
+    // this wavefront's root entries follow the stages' 64 words
+    int4 *rq = reinterpret_cast<int4 *>(reinterpret_cast<char *>(s_tmp) + 64 * 4) + (threadIdx.x >> 6) * kRootQ;
+    // nothing staged or counted as drained from before (Alternate's reports
+    // use the stage of ends)
+    st.nq = st.ne = 0;
+    st.dq = st.de = 0;
+    if (threadIdx.x == 0) s_tmp[kRootCnt] = 0;
+    __syncthreads();
+    bool any_end = false;
+    int fill = 0;  // root entries gathered in rq (wavefront-uniform)
+    // expands the newest n (<= 64) gathered entries
+    auto expand = [&](int n) {
+        wave_lds_sync();
+        const bool have = lane < n;
+        const int4 e = have ? rq[fill - n + lane] : make_int4(0, 0, 0, 0);
+        wave_lds_sync();
+        fill -= n;
+        expand_entries<WAVE, kAgent, PAIR>(g, e, have, ph, 0, flags, late, o, io, st, acc, any_end);
+    };
+    for (uint32_t base = wave * 64u * kStream; base < nc; base += nwaves * 64u * kStream) {
+        int cm[kStream], b[kStream], en[kStream];
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) {
+            const uint32_t c = min(base + 64u * u + (uint32_t)lane, nc - 1);
+            cm[u] = g.cmatch[c];
+            b[u] = g.colptr[c];
+            en[u] = g.colptr[c + 1];
+        }
+        // the step's roots are gathered first (its loads' registers are free
+        // again before any expansion), then expanded 64 at a time
+#pragma unroll
+        for (int u = 0; u < kStream; ++u) {
+            const uint32_t c = base + 64u * u + (uint32_t)lane;
+            const bool p = c < nc && cm[u] == -1 && en[u] > b[u];
+            const uint64_t m = __ballot(p);
+            if (p) rq[fill + (int)__popcll(m & lanemask_lt())] = make_int4((int)c, (int)c, b[u], en[u]);
+            if (lane == 0 && m) atomicAdd(&s_tmp[kRootCnt], (uint32_t)__popcll(m));
+            fill += __popcll(m);
+            if (flags & F_STATS) acc.add(S_ROOTS, p ? 1u : 0u);
+        }
+        while (fill >= 64) expand(64);
+    }
+    if (fill) expand(fill);
+    if ((flags & F_STATS) && threadIdx.x == 0 && wave == 0) acc.tick(S_PASS, 4ull * nc + nc / 8);
+    if ((flags & F_APSB) && __ballot(any_end) != 0 && lane == 0) atomicOr(io.found, 1u);
+    const uint32_t added = block_flush(st, next, g.ends, io.ecnt, s_tmp, false);
+    if (threadIdx.x == 0) {
+        if (g.rlist && s_tmp[kRootCnt]) atomicAdd(line(ctrl, (ph & 1) ? L_NRL1 : L_NRL0), s_tmp[kRootCnt]);
+        s_tmp[kBatchCtr] = 0;
+    }
+    return added;
 }
 
 // After the grid barrier that ends phase ph's root scan (no workgroup adds
@@ -1560,7 +1660,7 @@ DEV LvState small_levels(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, uin
         int4 *cur = (L & 1) ? g.fq1 : g.fq0;
         const LevelIO io{QSink{(L & 1) ? g.fq0 : g.fq1, &s_loc[(L + 1) % 3], nullptr, (flags & F_DEFER) != 0},
                          &s_loc[4], &s_loc[3], ctrl, false};
-        if (SINGLE && !(o.flags & F_MAXCLAIM))
+        if (SINGLE && pair_form(o.flags))
             expand_level<WAVE, kGroup, SINGLE, true>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
         else
             expand_level<WAVE, kGroup, SINGLE>(g, cur, n, wave, nwaves, ph, L, o, io, st, s_tmp, acc);
@@ -1657,8 +1757,20 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             if (!sync_all(none)) return false;
             s = LvState{0, 0, 0};
         } else {
-        const bool act = init_roots<SINGLE>(g, wave, nwaves, o, fc(0), st, s_tmp, acc, nullptr, ph, ctrl);
-        if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
+        bool act = false;
+        if (SINGLE && (flags & F_FUSE0) && !roots_listed(g, o, ph, ctrl)) {
+            // level 0 in the root scan's pass; the level loop goes on at 1
+            uint32_t share = pair_form(flags) ? roots_level0<WAVE, true>(g, wave, nwaves, o, ph, ctrl, st, s_tmp, acc)
+                                              : roots_level0<WAVE, false>(g, wave, nwaves, o, ph, ctrl, st, s_tmp, acc);
+            if (!(flags & F_APSB)) share &= 0x7fffffffu;
+            ++total_levels;
+            if (!sync(gr.n, Pub{1u, share & 0x7fffffffu, share >> 31, nullptr, nullptr, true}, share, false,
+                      NoWrite{}))
+                return false;
+        } else {
+            act = init_roots<SINGLE>(g, wave, nwaves, o, fc(0), st, s_tmp, acc, nullptr, ph, ctrl);
+            if (!sync_all(Pub{0, 0, 0, fc(0), nullptr, false})) return false;
+        }
         if (act && leader) mark_active_phase(ctrl, ph);
         reset_touch();
         for (;;) {
@@ -1691,7 +1803,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
                 const LevelIO io{next, line(ctrl, L_NENDS), fd(L % 3), ctrl, defer};
                 const uint32_t lw = active * (blockDim.x >> 6);
                 const uint32_t local = (!SINGLE || (flags & F_LEVELS)) ? 0u : o.local_levels;
-                if (SINGLE && !(flags & F_MAXCLAIM))
+                if (SINGLE && pair_form(flags))
                     share = expand_level<WAVE, kAgent, SINGLE, true>(g, cur, s.n, wave, lw, ph, L, o, io, st, s_tmp,
                                                                      acc, local);
                 else
@@ -1734,7 +1846,7 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
             alternate<kAgent>(g, ne, tid, nthreads, SINGLE ? flags : (flags & ~(uint32_t)F_FASTALT), ctrl, acc);
         if (!sync_all(none)) return false;
         // every block read the count of ends before this barrier; the next
-        // phase's BFS adds to it after the barrier that ends its root scan
+        // phase's BFS adds to it after the next grid barrier
         if (leader) *line(ctrl, L_NENDS) = 0;
         // FixMatching over the rows the walks touched, unless more were
         // reported than the list holds (then over every row)
@@ -1749,14 +1861,19 @@ DEV bool run_grid(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, const RunOpt
         // No grid barrier between FixMatching and the next root scan: the
         // scan reads cmatch, colptr and the root list, which FixMatching does
         // not write, and the BFS that reads the row words FixMatching writes
-        // starts after the scan's own barrier.  The unread frontier of an
-        // APsB stop is the exception: its slots are set back to -1 here, and
-        // the scan may write the same queue.
+        // starts after the scan's own barrier.  Two exceptions: the unread
+        // frontier of an APsB stop, whose slots are set back to -1 here in
+        // the queue the scan may write; and a next phase that expands level
+        // 0 in the scan's pass (its BFS reads row words before any other
+        // barrier).  Every block takes the same decision: the root count
+        // that roots_listed reads is final since this phase's first barrier.
+        const bool fuse_next = SINGLE && (flags & F_FUSE0) && !roots_listed(g, o, ph + 1, ctrl);
         if ((flags & F_DEFER) && left.stop) {
             const QSink lq{(left.L & 1) ? g.fq1 : g.fq0, nullptr, nullptr, true};
             for (uint32_t i = tid; i < left.n; i += nthreads) put_entry(lq, i, make_int4(-1, -1, -1, -1));
-            if (!sync_all(none)) return false;
         }
+        if (((flags & F_DEFER) && left.stop) || fuse_next)
+            if (!sync_all(none)) return false;
         if (timing) acc.tick(S_T_AUGMENT, wall_clock64() - ta);
     }
     if (leader) { *ph_out = ph; *lv_out = total_levels; }
@@ -1999,7 +2116,7 @@ __global__ void __launch_bounds__(1024) k_persistent_multi(const BatchDesc *desc
     // buffers (radj, prow, checked queues) a batch descriptor does not carry.
     // The kernel sits at the 128-register limit of a 1024-thread block;
     // without this its registers spill.
-    o.flags &= ~(uint32_t)(F_STATS | F_LEVELS | F_NOAUG | F_MAXCLAIM | F_DEFER | F_FASTALT | F_ASYNC);
+    o.flags &= ~(uint32_t)(F_STATS | F_LEVELS | F_NOAUG | F_MAXCLAIM | F_DEFER | F_FASTALT | F_ASYNC | F_FUSE0);
     const uint32_t q = blockIdx.x / group;
     const Grp gr{blockIdx.x % group, group};
     uint32_t *ctrl = ctrls + (size_t)q * L_NLINES * kLineWords;
@@ -2090,7 +2207,7 @@ __global__ void __launch_bounds__(1024) k_level(DevGraph g, uint32_t *ctrl, uint
                      line(ctrl, L_NENDS), line(ctrl, L_FOUND0 + L % 3), ctrl, false};
     __shared__ uint64_t s_acc[kAccN];
     Acc acc = make_acc(s_acc, stage_tmp(smem));
-    if (o.flags & F_MAXCLAIM)
+    if (!pair_form(o.flags))
         expand_level<WAVE, kAgent>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
     else
         expand_level<WAVE, kAgent, true, true>(g, cur, n, wave, nwaves, ph, L, o, io, st, stage_tmp(smem), acc);
@@ -2387,7 +2504,7 @@ static const void *persistent_fn(bool wave)
 
 hipError_t persistent_occupancy(bool wave, int block, int *blocks_per_cu)
 {
-    const int lds = stage_lds_bytes(block / 64);
+    const int lds = persistent_lds_bytes(block / 64);
     hipError_t e = allow_lds(persistent_fn(wave), lds);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, persistent_fn(wave), block, lds);
@@ -2402,7 +2519,7 @@ hipError_t launch_persistent(const DevGraph &g, uint32_t *ctrl, uint32_t *bar, c
     RunOpt oo = o;
     void *args[] = {&gg, &cc, &bb, &oo};
     return hipLaunchCooperativeKernel(persistent_fn(wave), dim3(blocks), dim3(block), args,
-                                      (unsigned)stage_lds_bytes(block / 64), st);
+                                      (unsigned)persistent_lds_bytes(block / 64), st);
 }
 
 hipError_t launch_init_roots(const DevGraph &g, uint32_t *ctrl, const RunOpt &o, hipStream_t st)

@@ -40,14 +40,14 @@ def test_options_roundtrip_and_rejects():
                  ("level_entries", "0"), ("idle_sleep", "32"), ("wr_check", "early"), ("wr_check", "late"), ("multi_threshold", "0"),
                  ("multi_group", "8"), ("max_blocks", "32"), ("endpoints", "one"), ("barrier", "counter"),
                  ("claim", "max"), ("claim", "probe"), ("flush", "atomic"), ("flush", "defer"),
-                 ("local_levels", "2"), ("local_levels", "auto"), ("local_edges", "0"), ("local_edges", "64"), ("wg_lds", "off"), ("wg_lds", "on"), ("alternate", "classic"), ("alternate", "fast"), ("roots", "list"), ("fix", "scan"), ("schedule", "async")]:
+                 ("local_levels", "2"), ("local_levels", "auto"), ("local_edges", "0"), ("local_edges", "64"), ("wg_lds", "off"), ("wg_lds", "on"), ("fuse", "off"), ("fuse", "on"), ("alternate", "classic"), ("alternate", "fast"), ("roots", "list"), ("fix", "scan"), ("schedule", "async")]:
         old = mcm.get_option(k)
         mcm.set_option(k, v)
         assert mcm.get_option(k) == v
         mcm.set_option(k, old)
     for k, v in [("driver", "x"), ("bfs", "fast"), ("block", "65"), ("nope", "1"), ("validate", "2"),
                  ("level_entries", "-1"), ("idle_sleep", "5000"), ("wr_check", "soon"), ("multi_group", "4096"),
-                 ("endpoints", "two"), ("barrier", "tree"), ("claim", "cas"), ("flush", "later"), ("local_levels", "17"), ("alternate", "slow"), ("local_edges", "-1"), ("wg_lds", "auto")]:
+                 ("endpoints", "two"), ("barrier", "tree"), ("claim", "cas"), ("flush", "later"), ("local_levels", "17"), ("alternate", "slow"), ("local_edges", "-1"), ("wg_lds", "auto"), ("fuse", "1")]:
         with pytest.raises(mcm.McmError) as e:
             mcm.set_option(k, v)
         assert e.value.code == mcm.MCM_EINVAL

@@ -35,7 +35,7 @@ DRIVER_COMBOS = [
 ]
 
 DEFAULTS = dict(driver="apfb", bfs="wr", mapping="auto", loop="auto", validate=0, stats=0, wg_threshold=16384,
-                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels="auto", local_edges=1024, wg_lds="on",
+                level_entries=128, idle_sleep=8, wr_check="auto", small_max=256, endpoints="auto", barrier="counter", claim="auto", flush="auto", local_levels="auto", local_edges=1024, wg_lds="on", fuse="on",
                 alternate="auto", schedule="levels", fix="auto", roots="auto")
 
 
@@ -370,6 +370,28 @@ def test_one_workgroup_lds(lds, combo, name):
     for _ in range(2):
         assert _gpu(g)[0] == ref, (lds, combo)
     assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (lds, combo)
+
+
+# BFS level 0 in the root scan's pass (probe claims; phases that do not list
+# their roots) and as a level of its own: both drivers, roots listed or
+# scanned, both Alternate forms (the recorded-row one leaves the two-edge
+# rounds), both FixMatching forms, low-degree graphs with probe claims too;
+# runs in a row on one workspace.
+@pytest.mark.parametrize("fuse", ["on", "off"])
+@pytest.mark.parametrize("combo", [dict(driver="apfb", roots="auto", fix="auto"),
+                                   dict(driver="apfb", roots="scan", fix="scan", alternate="fast"),
+                                   dict(driver="apsb", roots="auto", fix="list"),
+                                   dict(driver="apfb", roots="list", fix="auto", local_levels=0),
+                                   dict(driver="apfb", roots="auto", fix="auto", wr_check="late", endpoints="one")],
+                         ids=lambda c: "-".join(str(v) for v in c.values()))
+@pytest.mark.parametrize("name", ["rmat13", "rmat15", "grid128", "uniform2000"])
+def test_fused_level0(fuse, combo, name):
+    g = gg.workload(name)
+    ref = _oracle_card(g)
+    _set(wg_threshold=0, claim="probe", fuse=fuse, **combo)
+    for _ in range(2):
+        assert _gpu(g)[0] == ref, (fuse, combo)
+    assert _gpu(g, "empty", certify=False)[0] == _oracle_card(g, "empty"), (fuse, combo)
 
 
 def test_deferred_levels_repeated():
