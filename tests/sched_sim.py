@@ -234,6 +234,10 @@ def phase(colptr, rowind, cmatch, rmatch, rng, **kw):
     for r in np.flatnonzero(f.marked):
         rmatch[r] = -2
     touched = alternate(f, cmatch, rmatch, rng, walk=kw.get("walk", "recorded"), schedule=kw.get("schedule", "random"))
-    fix_matching(cmatch, rmatch, f.marked, touched if kw.get("fix", "scan") == "list" else None)
+    fix = kw.get("fix", "scan")
+    # "list": the rows the walks reported; "reached": the rows claimed in the
+    # phase (what the kernel's full scan gathers columns for); "scan": all
+    rows = touched if fix == "list" else (np.flatnonzero(f.pred >= 0) if fix == "reached" else None)
+    fix_matching(cmatch, rmatch, f.marked, rows)
     trees = len({int(f.root[f.pred[e]]) for e in f.ends})
     return f, trees

@@ -12,8 +12,10 @@ After every phase, whatever the schedule:
       recorded-row walk that has none, with several ends per tree sharing
       their way to the root;
   I4  no row is left marked -2.
-FixMatching runs over every row, or only over the rows the walks report
-(each row a walk writes, and the row a classic walk stops at).
+FixMatching runs over every row, only over the rows the walks report
+(each row a walk writes, and the row a classic walk stops at), or only over
+the rows claimed in the phase (the kernel's full scan gathers a row's column
+only for those: I5 below).
 Phases repeat until a BFS finds no end; the result then equals the
 oracle's maximum.  A planted mistake in FixMatching must break I1 or I4."""
 import random
@@ -65,7 +67,7 @@ KW = [dict(walk=w, schedule=s, order=o, wr=wr, one_end=oe, local_p=lp, fix=fx)
       for w in ("recorded", "classic") for s in ("random", "lockstep", "sequential")
       for o, lp in (("levels", 0.0), ("levels", 0.5), ("lockstep", 0.0), ("pool", 0.0))
       for wr, oe in ((True, False), (True, True), (False, False))
-      for fx in ("scan", "list")]
+      for fx in ("scan", "list", "reached")]
 
 
 @pytest.mark.parametrize("kw", KW, ids=lambda d: "-".join(f"{k}={v}" for k, v in d.items()))
@@ -160,3 +162,38 @@ def test_listed_fix_needs_the_stop_rows():
         assert caught
     finally:
         S._walk_classic = real
+
+
+@pytest.mark.parametrize("walk", ["recorded", "classic"])
+@pytest.mark.parametrize("one_end", [False, True])
+@pytest.mark.parametrize("order", ["levels", "pool"])
+def test_rows_outside_the_forest_stay_consistent(walk, one_end, order):
+    """I5: after Alternate, every row the phase's BFS did not claim is still
+    unmatched or matched to a column that points back, under every schedule:
+    a walk writes, stops at or leaves behind only claimed rows (the old mate
+    of a flipped column is the walk's next row, whose claim brought that
+    column into the tree).  So FixMatching may skip the other rows, and
+    matching with it to the end gives the maximum."""
+    rng = random.Random(zlib.crc32(f"{walk}{one_end}{order}".encode()))
+    for i, g in enumerate(_graphs()):
+        ref = O.hopcroft_karp(g, *O.cheap_init(g))[0]
+        for init in ("empty", "cheap"):
+            cm = np.full(g.nc, -1, np.int64)
+            rm = np.full(g.nr, -1, np.int64)
+            if init == "cheap":
+                c0, r0 = O.cheap_init(g)
+                cm[:], rm[:] = c0, r0
+            for _ in range(g.nc + 2):
+                f = S.bfs_phase(g.colptr, g.rowind, cm, rm, rng, order=order, one_end=one_end)
+                for r in np.flatnonzero(f.marked):
+                    rm[r] = -2
+                S.alternate(f, cm, rm, rng, walk=walk, schedule="random")
+                out = np.flatnonzero(f.pred < 0)
+                m = rm[out]
+                assert ((m == -1) | ((m >= 0) & (cm[np.maximum(m, 0)] == out))).all(), (i, init)
+                S.fix_matching(cm, rm, f.marked, np.flatnonzero(f.pred >= 0))
+                assert not (rm == -2).any()
+                assert _valid(g, cm.astype(np.int32), rm.astype(np.int32)) is not None
+                if not f.ends:
+                    break
+            assert int((cm >= 0).sum()) == ref, (i, g.name, init)
