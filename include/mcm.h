@@ -438,7 +438,7 @@ int64_t mcm_cheap_init_host(int32_t ncols, int32_t nrows, const int32_t *colptr,
  *                                              in Algorithm 1 (BFS trees are
  *                                              then shortest-path trees; the
  *                                              matching is maximum either
- *                                              way); auto = 12 with probe
+ *                                              way); auto = 16 with probe
  *                                              claims, 6 with atomic-maximum
  *                                              claims
  *   "local_edges" "1024" (default) | "0".."1048576"

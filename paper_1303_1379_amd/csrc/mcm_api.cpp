@@ -292,10 +292,10 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
     r.split = (uint32_t)o.split;
     r.level_entries = (uint32_t)o.level_entries;
     r.idle_sleep = (uint32_t)o.idle_sleep;
-    // auto: 12 where rows are probed before their claim (skewed graphs: rmat23
-    // 3.45 against 3.54 ms with 6), 6 with atomic-maximum claims (low-degree
-    // graphs: grid2048 slower with 10 or 16)
-    r.local_levels = o.local_levels >= 0 ? (uint32_t)o.local_levels : ((flags & F_MAXCLAIM) ? 6u : 12u);
+    // auto: 16 where rows are probed before their claim (skewed graphs: rmat23
+    // 3.08-3.10 ms against 3.13 with 12, same box), 6 with atomic-maximum
+    // claims (low-degree graphs: grid2048 no faster with 10 or 16)
+    r.local_levels = o.local_levels >= 0 ? (uint32_t)o.local_levels : ((flags & F_MAXCLAIM) ? 6u : 16u);
     r.local_edges = (uint32_t)o.local_edges;
     r.take = (uint32_t)std::min(o.take, 64);
     r.keep = (uint32_t)std::max(o.keep, o.take);

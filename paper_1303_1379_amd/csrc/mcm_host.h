@@ -92,7 +92,7 @@ struct Options {
     int claim = 2;            // row claim: 0 probe + compare-and-swap, 1 atomic maximum, 2 auto (by degree)
     int flush = 2;            // grid levels: 0 reserve by a queue atomic, 1 through the counter barrier, 2 auto (1)
     int local_levels = -1;    // grid levels: a wavefront expands its own new entries this many times more
-                              // (-1 = auto: 12 with probe claims, 6 with atomic-maximum claims)
+                              // (-1 = auto: 16 with probe claims, 6 with atomic-maximum claims)
     int local_edges = 1024;   // a local level takes the newest staged entries of at most this many edges (0 = 64 entries)
     int alternate = 2;        // mcm_match's Alternate: 0 classic, 1 recorded rows, 2 auto (1 on low degree)
     int schedule = 0;         // mcm_match's BFS: 0 level-synchronous, 1 level-free, 2 auto (= 0)

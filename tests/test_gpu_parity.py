@@ -297,7 +297,7 @@ def test_auto_claim_and_flush(name, low):
     assert _gpu(g, certify=False)[0] == ref
     s = mcm.last_stats()
     assert (s["claim"], s["flush"], s["wr_check"], s["alternate"]) == ((1, 1, 1, 1) if low else (0, 0, 0, 0))
-    assert s["local_levels"] == (6 if low else 12)
+    assert s["local_levels"] == (6 if low else 16)
     _set(loop="host")
     assert _gpu(g, certify=False)[0] == ref
     assert mcm.last_stats()["flush"] == 0
