@@ -1183,10 +1183,27 @@ DEV void mark_active_phase(uint32_t *ctrl, uint32_t ph)
 
 // Alternate (Algorithm 3) from every reached unmatched row, one thread per
 // row.  A walk that reaches a root (its column has no mate) ends there.
+// A pointer that is the same in every lane of the wave (every caller's graph
+// is one per workgroup or per grid), moved into scalar registers and hidden
+// from the optimiser, which then cannot hoist addresses derived from it out
+// of the loop around the call.
+DEV const int32_t *fresh_uniform(const int32_t *p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return reinterpret_cast<const int32_t *>(((uint64_t)hi << 32) | lo);
+}
+
 template <int S>
 DEV void alternate(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nthreads, uint32_t flags,
                    uint32_t *ctrl, Acc &acc)
 {
+    // the list of ends is read through a pointer the compiler takes as new
+    // in every call, so that no per-lane address into it stays live (and
+    // spilled) through a whole persistent loop
+    const int32_t *ends = fresh_uniform(g.ends);
     uint64_t steps = 0;
     int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);  // low word of rw[r] is rlo[2r]
     if (flags & F_FASTALT) {
@@ -1199,7 +1216,7 @@ DEV void alternate(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nth
         // wins and FixMatching unmatches the other walk's row, as it does
         // for a walk that stops there.
         for (uint32_t i = tid; i < nends; i += nthreads) {
-            int r = g.ends[i];
+            int r = ends[i];
             int c = ld_i<S>(&g.pred[r]);
             int r2 = ld_i<S>(&g.prow[r]);
             uint32_t guard = 0;
@@ -1228,7 +1245,7 @@ DEV void alternate(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nth
         return;
     }
     for (uint32_t i = tid; i < nends; i += nthreads) {
-        int r = g.ends[i];
+        int r = ends[i];
         int c = ld_i<S>(&g.pred[r]);
         uint32_t guard = 0;
         for (;;) {
@@ -1263,6 +1280,7 @@ template <int S>
 DEV void alternate_listed(const DevGraph &g, uint32_t nends, uint32_t tid, uint32_t nthreads, uint32_t flags,
                           uint32_t *ctrl, Acc &acc, Stage &st, uint32_t *tcnt)
 {
+    const int32_t *ends = fresh_uniform(g.ends);  // as in alternate
     uint64_t steps = 0;
     int32_t *rlo = reinterpret_cast<int32_t *>(g.rw);
     const bool fast = (flags & F_FASTALT) != 0;
@@ -1274,7 +1292,7 @@ DEV void alternate_listed(const DevGraph &g, uint32_t nends, uint32_t tid, uint3
     // column's range: one round trip per step)
     int r = 0, c = 0, r2 = -1;
     auto start = [&]() {
-        r = g.ends[i];
+        r = ends[i];
         c = ld_i<S>(&g.pred[r]);
         if (fast) r2 = ld_i<S>(&g.prow[r]);
     };

@@ -1,9 +1,10 @@
 """Register budget of the launches whose workgroups must all be resident at
 once (cooperative launches that spin at grid barriers): compiled for gfx950,
 they stay within the 128 registers per lane of a 1024-thread workgroup and
-do not spill, except for one 8-byte value of the single-graph kernel with
-the wave mapping (a per-lane address it reloads once per phase, at the start
-of Alternate), which the limit below allows and no more.  The multi-graph
+do not spill.  The single-graph kernel with the wave mapping sits at the
+limit: a per-lane address into the list of augmenting-path ends, once kept
+live through its whole phase loop, spilled until Alternate took that list
+through a pointer the compiler cannot hoist.  The multi-graph
 kernel sits close to the limit, and small additions have pushed it over
 before.  No GPU needed: hipcc reports each kernel's resources at compile
 time."""
@@ -47,6 +48,5 @@ def test_cooperative_kernels_do_not_spill():
     coop = {k: v for k, v in kernels.items() if any(f"{n}I" in k for n in COOPERATIVE)}
     assert len(coop) >= 4, sorted(kernels)          # both mappings of both persistent kernels
     for name, r in coop.items():
-        allowed = 16 if name.startswith("_ZN3mcm12k_persistentILb1E") else 0
-        assert r.get("ScratchSize", 0) <= allowed, (name, r)
+        assert r.get("ScratchSize", 0) == 0, (name, r)
         assert r.get("VGPRs", 0) <= 128, (name, r)
