@@ -264,16 +264,19 @@ int64_t ensure_desc(Workspace &w, size_t n)
 uint32_t *ctrl_line(uint32_t *ctrl, int l) { return ctrl + l * kLineWords; }
 
 // Frontier entries per level: one per column, plus one per `split` edges
-// of a split column.  Reads nnz = colptr[nc] from the device.
+// of a split column.  Reads nnz = colptr[nc] from the device (into pinned
+// memory when the caller gives some: a pageable target costs a staged copy).
 int64_t queue_capacity(int32_t nc, const int32_t *colptr, uint32_t split, hipStream_t st, size_t *qcap,
-                       int64_t *nnz_out)
+                       int64_t *nnz_out, int32_t *staging)
 {
     *qcap = (size_t)nc + 1;
     if (nnz_out) *nnz_out = -1;
     if (split == 0 && !nnz_out) return 0;
-    int32_t nnz = 0;
-    HIPCHK(hipMemcpyAsync(&nnz, colptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int32_t word = 0;
+    int32_t *dst = staging ? staging : &word;
+    HIPCHK(hipMemcpyAsync(dst, colptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    const int32_t nnz = *dst;
     if (nnz < 0) return fail(MCM_EINVAL, "colptr[ncols] = %d < 0", nnz);
     if (nnz_out) *nnz_out = nnz;
     if (split != 0) *qcap += (size_t)nnz / split + 1;
@@ -310,8 +313,12 @@ RunOpt run_opt(const Options &o, uint32_t flags, int64_t nc, const DevInfo &info
 
 // Runs the phase loop on one graph whose state was set up by launch_setup.
 // flags decides APFB/APsB, WR, NOAUG.  Returns 0 or a negative status; the
-// control block is copied to b.h_ctrl (stream synchronised).
-int64_t run_graph(const RunBufs &b, const Options &o, const DevGraph &g, uint32_t flags, hipStream_t st, int *loop_used)
+// control block is copied to b.h_ctrl (stream synchronised), except after
+// the persistent kernel when `sync_ctrl` is false: then the copies are left
+// to the caller, which queues more work first (mcm_match's finish kernel),
+// and one synchronisation serves both.
+int64_t run_graph(const RunBufs &b, const Options &o, const DevGraph &g, uint32_t flags, hipStream_t st, int *loop_used,
+                  bool sync_ctrl = true)
 {
     const bool wave = (flags & F_WAVE) != 0;
     int loop = o.loop;
@@ -334,9 +341,10 @@ int64_t run_graph(const RunBufs &b, const Options &o, const DevGraph &g, uint32_
         if (b.ev0) HIPCHK(hipEventRecord(b.ev0, st));
         HIPCHK(launch_persistent(g, b.ctrl, b.bar, ro, wave, blocks, o.block, st));
         if (b.ev1) HIPCHK(hipEventRecord(b.ev1, st));
-        HIPCHK(hipMemcpyAsync(b.h_ctrl, b.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
         if ((flags & F_STATS) && g.ptrace && b.h_ptrace)
             HIPCHK(hipMemcpyAsync(b.h_ptrace, g.ptrace, sizeof(uint32_t) * 2 * kPhaseTrace, hipMemcpyDeviceToHost, st));
+        if (!sync_ctrl) return 0;
+        HIPCHK(hipMemcpyAsync(b.h_ctrl, b.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         return 0;
     }
@@ -614,7 +622,8 @@ int64_t match_run(const RunBufs &b, const Options &o, uint32_t flags, bool singl
     g.qcap = b.cap_q;
     CoopHold hold(owner, st);  // at most one cooperative launch in flight in the process
     HIPCHK(launch_setup(g, init_cmatch, init_rmatch, b.ctrl, b.bar, flags, st));
-    if ((rc = run_graph(b, o, g, flags, st, &loop))) return rc;
+    // the control block is read once, after the finish kernel
+    if ((rc = run_graph(b, o, g, flags, st, &loop, false))) return rc;
     HIPCHK(launch_finish(g, out_rmatch, b.ctrl, st));
     HIPCHK(hipMemcpyAsync(b.h_ctrl, b.ctrl, (size_t)L_NLINES * 128, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -955,10 +964,12 @@ int64_t mcm_match(int32_t ncols, int32_t nrows, const int32_t *colptr, const int
     const bool single_wg = (int64_t)ncols + nrows <= o.wg_threshold;
     size_t qcap = 0;
     int64_t nnz = -1;
+    // (the pinned control-block copy is free until the run reads it back)
     if ((rc = queue_capacity(ncols, colptr, single_wg ? 0u : (uint32_t)o.split, st, &qcap,
                              single_wg || (o.claim != 2 && o.flush != 2 && o.wr_check != 2 && o.alternate != 2)
                                  ? nullptr
-                                 : &nnz)))
+                                 : &nnz,
+                             reinterpret_cast<int32_t *>(w.h_ctrl))))
         return rc;
     if ((rc = ensure_graph(w, (size_t)ncols, (size_t)nrows, std::max(qcap, (size_t)ncols)))) return rc;
     if (single_wg && (rc = ensure_desc(w, 1))) return rc;

@@ -211,9 +211,10 @@ int64_t check_graph_args(int32_t nc, int32_t nr, const int32_t *colptr, const in
 int64_t check_null_rowind(int32_t nc, int32_t nr, const int32_t *colptr, const int32_t *rowind, hipStream_t st);
 // Frontier entries per level (nc + 1, plus one per `split` edges when split
 // is on); reads nnz = colptr[nc] from the device when split is on or
-// nnz_out is given.
+// nnz_out is given, through `staging` (pinned host memory, a word the
+// caller owns for the call) when it is not NULL.
 int64_t queue_capacity(int32_t nc, const int32_t *colptr, uint32_t split, hipStream_t st, size_t *qcap,
-                       int64_t *nnz_out);
+                       int64_t *nnz_out, int32_t *staging = nullptr);
 // The row-claim, flush, root-test, Alternate and BFS-schedule forms of one
 // mcm_match run (nnz < 0 when unknown).
 uint32_t match_flags(const Options &o, int32_t nc, int32_t nr, int64_t nnz, bool single_wg);
