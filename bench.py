@@ -67,11 +67,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload):
-    """HBM bytes per launch of the persistent kernel from the committed
-    rocprofv3 counter summary (lines "key: value"), or None when missing or
-    taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"k_persistent_{workload}_traffic.txt")
+def load_traffic(workload, kernel="k_persistent", plan_config=None):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (lines "key: value"), or None when missing,
+    taken on other kernel sources, or (batched plans) on another launch
+    configuration than `plan_config`."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     d = {}
@@ -81,6 +82,8 @@ def load_traffic(workload):
             if sep:
                 d[k.strip()] = v.strip()
     if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if plan_config is not None and d.get("plan_config") != plan_config:
         return None
     try:
         return float(d["hbm_bytes_per_launch"])
@@ -159,6 +162,11 @@ def roofline(b, avg_s, kernel, traffic=None):
             "alg_bytes_per_launch": int(b), "avg_launch_ms": round(avg_s * 1000.0, 4)}
 
 
+def plan_config(info):
+    """The launch configuration of a batch plan, as its traffic summary names it."""
+    return f"mapping={info['mapping']} block={info['block']} blocks={info['blocks']} batch_min={info['batch_min']}"
+
+
 def bench_batched(ngraphs, steps, cpu_budget_s=0.0):
     """Uneven batch (graph g: seed mix(4, g), sizes log-uniform in [64, 65536],
     degrees 2..12, half uniform / half banded, 2 % columns emptied): one
@@ -216,7 +224,8 @@ def bench_batched(ngraphs, steps, cpu_budget_s=0.0):
             "loop_graphs_per_s": round(ngraphs / t_loop, 1), "loop_ms": round(t_loop * 1000, 3),
             "ratio": round(t_loop / t_b, 2),
             "identical_cardinalities": loop_cards == cards.tolist() == scards.tolist(),
-            "roofline": roofline(alg_bytes(st), float(np.mean(kms)) / 1000.0, "k_match_wg"),
+            "roofline": roofline(alg_bytes(st), float(np.mean(kms)) / 1000.0, "k_match_wg",
+                                 load_traffic("batched", "k_match_wg", plan_config(info))),
             "edges_scanned": st["edges_scanned"], "plan": info, "generate_s": round(t_gen, 2),
             **({"cpu_baseline": oracle_batch(graphs, cards, cpu_budget_s)} if cpu_budget_s > 0 else {})}
 
