@@ -163,8 +163,11 @@ def roofline(b, avg_s, kernel, traffic=None):
 
 
 def plan_config(info):
-    """The launch configuration of a batch plan, as its traffic summary names it."""
-    return f"mapping={info['mapping']} block={info['block']} blocks={info['blocks']} batch_min={info['batch_min']}"
+    """The kernel instance and launch shape of a batch plan, as its traffic
+    summary names them (the plan's batch_min, how many frontier entries a
+    wavefront takes at a time, splits the same reads differently and is
+    not part of the key)."""
+    return f"mapping={info['mapping']} block={info['block']} blocks={info['blocks']}"
 
 
 def bench_batched(ngraphs, steps, cpu_budget_s=0.0):
