@@ -64,3 +64,20 @@ def test_traffic_profile_lookup(bench):
         if t is not None:
             assert t > 0
     assert bench.load_traffic("no-such-workload") is None
+
+
+def test_batched_traffic_lookup(bench):
+    # the batch summary is read only for the kernel instance and launch shape
+    # it was taken on (mapping, block, blocks), whatever the plan's batch_min
+    path = os.path.join(ROOT, "profiles", "k_match_wg_batched_traffic.txt")
+    assert os.path.exists(path)
+    with open(path) as f:
+        text = f.read()
+    current = f"kernel_source_hash: {bench.kernel_source_hash()}" in text
+    shape = dict(mapping="wave", block=1024, blocks=256)
+    assert f"plan_config: {bench.plan_config(dict(shape, batch_min=1))}" in text
+    for bm in (1, 32):
+        t = bench.load_traffic("batched", "k_match_wg", bench.plan_config(dict(shape, batch_min=bm)))
+        assert (t is not None) == current
+    for other in (dict(shape, mapping="thread"), dict(shape, block=512), dict(shape, blocks=128)):
+        assert bench.load_traffic("batched", "k_match_wg", bench.plan_config(dict(other, batch_min=32))) is None
